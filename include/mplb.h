@@ -1,0 +1,247 @@
+/*
+ * mplb.h -- C ABI of the MI355X (gfx950) multiphase lattice Boltzmann library.
+ *
+ * One time step advances two coupled population sets on a regular lattice
+ * (arXiv 2101.06769):
+ *   - conservative Allen-Cahn phase-field populations g (Sec. 2.2): BGK
+ *     collision toward a second-order equilibrium plus the antidiffusion
+ *     source, order parameter phi = sum_a g_a;
+ *   - pressure-based low-Mach flow populations f' (Sec. 2.3): preconditioned
+ *     populations, cumulant collision (viscosity on the second-order
+ *     off-diagonal and deviatoric cumulants, all other rates unity), source
+ *     Xi carrying the density gradient, surface tension mu grad(phi) and the
+ *     body force;
+ * coupled through isotropic finite-difference gradients and Laplacians of
+ * phi (Sec. 2.2) and the linear density interpolation rho(phi) (Sec. 2.3).
+ * Lattices: D2Q9 (dim 2) and D3Q27 (dim 3).  Lattice units: dt = dx = 1,
+ * cs^2 = 1/3, heavy density 1 (Sec. 3).
+ *
+ * Conventions
+ *   - Every function returns an int status (MPLB_OK = 0, negative on error)
+ *     unless stated; none throws.  mplb_last_error() gives a message for the
+ *     most recent failure on the calling thread.
+ *   - Host arrays are double precision, C order with x fastest:
+ *     scalar fields [nz][ny][nx]; vector fields [dim][nz][ny][nx];
+ *     populations [Q][nz][ny][nx].
+ *   - Population order a = (cx+1) + 3 (cy+1) [+ 9 (cz+1)]: velocity
+ *     components are read off the base-3 digits of a.  Opposite: Q-1-a.
+ *   - "State at time n" means the pre-collision populations at every cell
+ *     (after streaming).  The library stores post-collision values and
+ *     streams by pulling, but every exchange through this header uses the
+ *     pre-collision view.
+ *   - Ownership: the caller owns the device arena (any device allocation of
+ *     at least mplb_state_bytes() bytes, e.g. a torch uint8 tensor) and all
+ *     host buffers.  The library carves the arena and never allocates or
+ *     frees device memory; it owns only its handle.
+ *   - Stream: all device work is queued on the hipStream_t given at create
+ *     time (NULL = the null stream).  Calls are asynchronous unless stated;
+ *     calls that return host data synchronise that stream.
+ *   - One handle per stream; handles are not thread-safe.
+ */
+#ifndef MPLB_H
+#define MPLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPLB_VERSION 1
+
+enum {
+    MPLB_OK = 0,
+    MPLB_EINVAL = -1,    /* invalid argument or parameter */
+    MPLB_ENOMEM = -2,    /* arena smaller than mplb_state_bytes() */
+    MPLB_EDEVICE = -3,   /* HIP runtime error (message in mplb_last_error) */
+    MPLB_EUNSTABLE = -4, /* non-finite value found by mplb_reduce */
+    MPLB_ESTATE = -5     /* call not valid in the handle's current state */
+};
+
+/* Boundary type per axis (both faces of that axis). */
+enum {
+    MPLB_BC_PERIODIC = 0,
+    MPLB_BC_WALL = 1,    /* half-way bounce-back no-slip wall (Sec. 3.2, 3.4);
+                            phi ghost layer mirrors the first fluid layer */
+    MPLB_BC_SYMMETRY = 2 /* specular free-slip plane (Sec. 3.4, side walls) */
+};
+
+/* Population storage format.  Arithmetic is FP64 for MPLB_STORE_FP64 and
+ * FP32 otherwise; global reductions are always FP64. */
+enum {
+    MPLB_STORE_FP64 = 0,
+    MPLB_STORE_FP32 = 1,
+    MPLB_STORE_FP16S = 2,    /* f' as FP16 deviations from w p_h, scaled by w rho cs^2;
+                                g FP32 */
+    MPLB_STORE_FP16S_ALL = 3 /* f' as above, g as FP16 deviations from w phi */
+};
+
+/* Flow collision operator. */
+enum {
+    MPLB_COLL_CUMULANT = 0, /* the paper's operator (Sec. 2.3) */
+    MPLB_COLL_SRT = 1       /* single-relaxation-time form of the same kinetic
+                               equation (Sec. 2.3, BGK collision), for comparison */
+};
+
+/* Fields for mplb_read. */
+enum {
+    MPLB_FIELD_PHI = 0, /* order parameter, sum_a g_a */
+    MPLB_FIELD_RHO = 1, /* rho_l + (rho_h - rho_l) phi */
+    MPLB_FIELD_UX = 2,  /* velocity: first moment of f'/(rho cs^2) plus F/(2 rho) */
+    MPLB_FIELD_UY = 3,
+    MPLB_FIELD_UZ = 4,
+    MPLB_FIELD_P = 5    /* hydrodynamic pressure: sum f' + sum Xi / 2 */
+};
+
+/* Problem statement (Sec. 2.1-2.3, Sec. 3): lattice, densities, viscosities,
+ * interface width, mobility, surface tension, gravity, boundaries. */
+typedef struct mplb_params {
+    int32_t dim;          /* 2 -> D2Q9, 3 -> D3Q27 */
+    int32_t n[3];         /* nx, ny, nz (nz = 1 in 2-D); each >= 1 */
+    int32_t bc[3];        /* MPLB_BC_* per axis; z ignored in 2-D */
+    double rho_heavy;     /* rho_h > 0 (1 in the paper's units) */
+    double rho_light;     /* rho_l > 0 */
+    double nu_heavy;      /* kinematic viscosity of the heavy phase, > 0 */
+    double nu_light;      /* kinematic viscosity of the light phase, > 0;
+                             tau = nu/cs^2, omega = 1/(tau + 1/2) */
+    double W;             /* interface thickness, >= 1 (cells) */
+    double mobility;      /* M > 0; tau_phi = M/cs^2, taubar_phi = tau_phi + 1/2 */
+    double sigma;         /* surface tension >= 0; beta = 12 sigma/W, kappa = 3 sigma W/2 */
+    double gravity[3];    /* body-force acceleration, F_b = rho g; g[2] = 0 in 2-D */
+    int32_t storage;      /* MPLB_STORE_* */
+    int32_t visc_interp;  /* 0: nu = nu_l + (nu_h - nu_l) phi; 1: rho nu linear in phi */
+    int32_t collision;    /* MPLB_COLL_* */
+    int32_t reserved;     /* must be 0 */
+} mplb_params;
+
+typedef struct mplb_solver mplb_solver;
+
+/* Library version (MPLB_VERSION) and the device architecture it was built for. */
+int32_t mplb_version(void);
+const char *mplb_arch(void);
+
+/* Bytes of device memory a solver with these parameters needs (0 if the
+ * parameters are invalid). */
+size_t mplb_state_bytes(const mplb_params *p);
+
+/* Validate p and bind a solver to the caller's arena and stream.
+ * dev_arena: device pointer, 256-byte aligned, at least mplb_state_bytes(p).
+ * hip_stream: a hipStream_t (NULL for the null stream).
+ * Errors: EINVAL (bad parameters, see mplb_last_error), ENOMEM (arena too small). */
+int mplb_create(const mplb_params *p, void *dev_arena, size_t arena_bytes, void *hip_stream,
+                mplb_solver **out);
+
+/* Initial state from macroscopic fields (host, double): phi [N], u [dim][N],
+ * p [N] (NULL = zero pressure).  Populations become the equilibria (Sec. 2.2,
+ * 2.3, Appendix A) at the velocity u - F/(2 rho) and pressure p - sum(Xi)/2,
+ * so that mplb_read returns exactly phi, u and p before the first step.
+ * Resets the step counter.  Synchronises the stream. */
+int mplb_init(mplb_solver *s, const double *phi, const double *u, const double *p);
+
+/* Advance nsteps >= 0 time steps (asynchronous). */
+int mplb_step(mplb_solver *s, int64_t nsteps);
+
+/* As mplb_step, but records HIP events around every kernel launch on the
+ * solver's stream and returns the summed device time of the two kernels of
+ * the step (ms_phi: order-parameter pass; ms_collide: fused collision) in
+ * milliseconds.  Synchronises the stream.  For profiling; the events add a
+ * few microseconds per step. */
+int mplb_step_timed(mplb_solver *s, int64_t nsteps, double *ms_phi, double *ms_collide);
+
+/* Block until all queued work on the solver's stream has finished. */
+int mplb_sync(mplb_solver *s);
+
+/* Steps taken since mplb_init / mplb_set_populations. */
+int64_t mplb_steps_done(const mplb_solver *s);
+
+/* One macroscopic field (MPLB_FIELD_*) of the state at time n into host_out[N].
+ * Synchronises the stream. */
+int mplb_read(mplb_solver *s, int32_t field, double *host_out);
+
+/* FP64 reductions over the lattice, deterministic (fixed summation order):
+ * out[0] = sum phi, out[1..3] = sum rho u, out[4] = max |u|.
+ * Returns MPLB_EUNSTABLE if any phi, rho u or |u| is not finite.
+ * Synchronises the stream. */
+int mplb_reduce(mplb_solver *s, double out[5]);
+
+/* Pre-collision populations of the state at time n (which: 0 = f', 1 = g),
+ * host_out[Q][N] in the population order above.  Synchronises the stream. */
+int mplb_get_populations(mplb_solver *s, int32_t which, double *host_out);
+
+/* Replace one population set of the state at time n (which: 0 = f', 1 = g)
+ * with host_in[Q][N] (pre-collision values, population order above).
+ * Synchronises the stream. */
+int mplb_set_populations(mplb_solver *s, int32_t which, const double *host_in);
+
+/* Threads per block used for the step kernels (x, y, z); 0 = library default.
+ * The product must be a multiple of 64 and at most 1024. */
+int mplb_set_block(mplb_solver *s, int32_t bx, int32_t by, int32_t bz);
+
+/* Autotuner: time candidate block shapes for the step kernels (each over
+ * `steps` steps after two warm-up steps, device time from HIP events), select
+ * the fastest, and write it to best[3].  The solver is advanced by the timed
+ * steps, so tune on a scratch solver of representative size.  candidates is
+ * an array of ncand (bx, by, bz) triples, or NULL for the built-in list. */
+int mplb_tune_block(mplb_solver *s, int32_t steps, const int32_t *candidates, int32_t ncand,
+                    int32_t best[3], double *best_ms_per_step);
+
+/* Release the handle (the arena stays the caller's). */
+void mplb_destroy(mplb_solver *s);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent solvers of one dimension and storage format
+ * advance together, two persistent launches per step over a tile list that
+ * covers every attached lattice (each tile one block of the batch's block
+ * shape).  Each attached solver has its own parameters, lattice size and
+ * activity window; a solver's result is identical whether it is stepped
+ * alone or in a batch (same per-cell arithmetic).  Steps are replayed from a
+ * captured hipGraph in chunks of `graph_chunk` steps.
+ * ------------------------------------------------------------------------- */
+typedef struct mplb_batch mplb_batch;
+
+/* Device bytes of the batch tables for `capacity` solvers and `max_tiles`
+ * tiles in total. */
+size_t mplb_batch_table_bytes(int32_t capacity, int64_t max_tiles);
+
+/* dev_table: 256-byte aligned device memory of mplb_batch_table_bytes();
+ * hip_stream must be the stream of every solver that will be attached. */
+int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t max_tiles,
+                      void *dev_table, size_t table_bytes, void *hip_stream, mplb_batch **out);
+
+/* Block (= tile) shape of the batched kernels; at most 256 threads.
+ * Rebuilds the tile list. */
+int mplb_batch_set_block(mplb_batch *b, int32_t bx, int32_t by, int32_t bz);
+
+/* Graph chunk in steps (>= 1), or 0 to launch every step directly. */
+int mplb_batch_set_graph_chunk(mplb_batch *b, int32_t chunk);
+
+/* Attach an initialised solver for the next nsteps batch steps; *slot
+ * receives its slot.  The solver must not step on its own while attached.
+ * Errors: EINVAL (dimension/storage/stream mismatch), ENOMEM (no free slot
+ * or tile list full), ESTATE (solver not initialised or already attached). */
+int mplb_batch_attach(mplb_batch *b, mplb_solver *s, int64_t nsteps, int32_t *slot);
+
+/* Detach the solver in `slot` (its state stays valid and readable). */
+int mplb_batch_detach(mplb_batch *b, int32_t slot);
+
+/* Advance the batch by nsteps (asynchronous): every attached solver whose
+ * window covers a step is advanced by it. */
+int mplb_batch_step(mplb_batch *b, int64_t nsteps);
+
+/* Steps the solver in `slot` still has to take (0 = finished). */
+int mplb_batch_remaining(const mplb_batch *b, int32_t slot, int64_t *remaining);
+
+/* Batch steps taken so far. */
+int64_t mplb_batch_steps_done(const mplb_batch *b);
+
+/* Release the batch handle and its graph (attached solvers are detached). */
+void mplb_batch_destroy(mplb_batch *b);
+
+/* Message describing the last failed call on this thread ("" if none). */
+const char *mplb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -147,6 +147,11 @@ def set_threads(n: int):
     _load().orc_set_threads(int(n))
 
 
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().orc_num_threads())
+
+
 def ncells(p: Params) -> int:
     return p.n[0] * p.n[1] * p.n[2]
 

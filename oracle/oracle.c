@@ -135,6 +135,15 @@ void orc_set_threads(int nthreads)
 #endif
 }
 
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 static int check_params(const orc_params *p)
 {
     if (p->dim != 2 && p->dim != 3) return -1;

@@ -44,6 +44,7 @@ typedef struct {
 int  orc_Q(int dim);
 void orc_lattice(int dim, int *c /* Q*3 */, double *w /* Q */, int *opp /* Q */);
 void orc_set_threads(int nthreads);
+int  orc_num_threads(void);
 
 int orc_gradients(const orc_params *p, const double *phi, double *grad, double *lap);
 int orc_init(const orc_params *p, const double *phi, const double *u, const double *ph,

@@ -1,0 +1,774 @@
+// C ABI of the multiphase lattice Boltzmann library (declarations and the
+// contract of every call: include/mplb.h).
+//
+// Device memory layout inside the caller's arena (each region 256-byte
+// aligned, np = cell count rounded up to a multiple of 64):
+//   F0 G0 F1 G1   populations, [Q][np] each, ping-pong pairs; Fk and Gk are
+//                 adjacent so that the idle pair doubles as a staging area for
+//                 host transfers
+//   phi           order parameter of the current time level, [np]
+//   fp, fr, gp    per-cell shift/scale of FP16-shifted sets, two of each
+//   partials      reduction partial sums, result
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mplb.h"
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(MPLB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+constexpr int RED_PARTIALS = 1024;
+
+size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    int Q;
+    long long N, np;
+    size_t sF, sG, sT;
+    size_t F[2], G[2], phi, fp[2], fr[2], gp[2], partials, result, total;
+    size_t staging_bytes;
+};
+
+bool validate(const mplb_params *p, std::string &why)
+{
+    if (!p) return why = "params is NULL", false;
+    if (p->dim != 2 && p->dim != 3) return why = "dim must be 2 or 3", false;
+    for (int i = 0; i < 3; ++i)
+        if (p->n[i] < 1) return why = "every lattice extent must be >= 1", false;
+    if (p->dim == 2 && p->n[2] != 1) return why = "nz must be 1 in 2-D", false;
+    const long long N = (long long)p->n[0] * p->n[1] * p->n[2];
+    if (N > 0x7fffffffLL - 64) return why = "lattice has more than 2^31 cells", false;
+    for (int i = 0; i < p->dim; ++i)
+        if (p->bc[i] < MPLB_BC_PERIODIC || p->bc[i] > MPLB_BC_SYMMETRY)
+            return why = "unknown boundary type", false;
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    if (!pos(p->rho_heavy) || !pos(p->rho_light)) return why = "densities must be > 0", false;
+    if (!pos(p->nu_heavy) || !pos(p->nu_light)) return why = "viscosities must be > 0", false;
+    if (!std::isfinite(p->W) || p->W < 1.0) return why = "interface thickness W must be >= 1", false;
+    if (!pos(p->mobility)) return why = "mobility must be > 0", false;
+    if (!std::isfinite(p->sigma) || p->sigma < 0.0) return why = "surface tension must be >= 0", false;
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(p->gravity[i])) return why = "gravity must be finite", false;
+    if (p->dim == 2 && p->gravity[2] != 0.0) return why = "gravity[2] must be 0 in 2-D", false;
+    if (p->storage < MPLB_STORE_FP64 || p->storage > MPLB_STORE_FP16S_ALL)
+        return why = "unknown storage format", false;
+    if (p->visc_interp != 0 && p->visc_interp != 1) return why = "visc_interp must be 0 or 1", false;
+    if (p->collision != MPLB_COLL_CUMULANT && p->collision != MPLB_COLL_SRT)
+        return why = "unknown collision operator", false;
+    if (p->reserved != 0) return why = "reserved must be 0", false;
+    return true;
+}
+
+Layout make_layout(const mplb_params *p)
+{
+    Layout L{};
+    L.Q = p->dim == 2 ? 9 : 27;
+    L.N = (long long)p->n[0] * p->n[1] * p->n[2];
+    L.np = (L.N + 63) / 64 * 64;
+    const bool f16 = p->storage == MPLB_STORE_FP16S || p->storage == MPLB_STORE_FP16S_ALL;
+    L.sF = p->storage == MPLB_STORE_FP64 ? 8 : f16 ? 2 : 4;
+    L.sG = p->storage == MPLB_STORE_FP64 ? 8 : p->storage == MPLB_STORE_FP16S_ALL ? 2 : 4;
+    L.sT = p->storage == MPLB_STORE_FP64 ? 8 : 4;
+    size_t off = 0;
+    const size_t bF = up(L.Q * L.np * L.sF, ALIGN), bG = up(L.Q * L.np * L.sG, ALIGN);
+    for (int k = 0; k < 2; ++k) {
+        L.F[k] = off;
+        off += bF;
+        L.G[k] = off;
+        off += bG;
+    }
+    L.staging_bytes = bF + bG;
+    L.phi = off;
+    off += up(L.np * L.sT, ALIGN);
+    const size_t bref = up(L.np * 4, ALIGN);
+    for (int k = 0; k < 2; ++k) {
+        L.fp[k] = L.fr[k] = L.gp[k] = 0;
+        if (f16) {
+            L.fp[k] = off;
+            off += bref;
+            L.fr[k] = off;
+            off += bref;
+        }
+        if (p->storage == MPLB_STORE_FP16S_ALL) {
+            L.gp[k] = off;
+            off += bref;
+        }
+    }
+    L.partials = off;
+    off += up(RED_PARTIALS * 8 * sizeof(double), ALIGN);
+    L.result = off;
+    off += up(8 * sizeof(double), ALIGN);
+    L.total = off;
+    return L;
+}
+
+dim3 default_block(const mplb_params *p)
+{
+    auto pow2 = [](int v, int cap) {
+        int b = 1;
+        while (b < v && b < cap) b <<= 1;
+        return b;
+    };
+    const int bx = pow2(p->n[0], 64);
+    const int by = pow2(p->n[1], 256 / bx);
+    const int bz = pow2(p->n[2], 256 / (bx * by));
+    return dim3(bx, by, bz);
+}
+
+mplb::PhysD make_phys(const mplb_params *p)
+{
+    mplb::PhysD d{};
+    d.rho_l = p->rho_light;
+    d.drho = p->rho_heavy - p->rho_light;
+    d.nu_l = p->nu_light;
+    d.dnu = p->nu_heavy - p->nu_light;
+    d.rnu_l = p->rho_light * p->nu_light;
+    d.drnu = p->rho_heavy * p->nu_heavy - p->rho_light * p->nu_light;
+    d.beta = 12.0 * p->sigma / p->W;
+    d.kappa = 1.5 * p->sigma * p->W;
+    d.gx = p->gravity[0];
+    d.gy = p->gravity[1];
+    d.gz = p->dim == 3 ? p->gravity[2] : 0.0;
+    const double tpb = p->mobility * 3.0 + 0.5;
+    d.inv_tpb = 1.0 / tpb;
+    d.src_pre = 1.0 - 0.5 / tpb;
+    d.four_W = 4.0 / p->W;
+    d.visc_interp = p->visc_interp;
+    d.collision = p->collision;
+    return d;
+}
+
+}  // namespace
+
+struct mplb_solver {
+    mplb_params prm;
+    Layout L;
+    char *base;
+    hipStream_t stream;
+    int cur;
+    int64_t steps;
+    bool ready;
+    bool attached;
+    dim3 block;
+    mplb::PhysD ph;
+
+    void *at(size_t off) const { return off ? base + off : nullptr; }
+    void *F(int k) const { return base + L.F[k]; }
+    void *G(int k) const { return base + L.G[k]; }
+    double *staging(int k) const { return reinterpret_cast<double *>(base + L.F[k]); }
+
+    // Context for work that reads buffer `in` and writes buffer 1 - in.
+    mplb::Ctx ctx(int in) const
+    {
+        mplb::Ctx c{};
+        c.dim = prm.dim;
+        c.storage = prm.storage;
+        c.g.nx = prm.n[0];
+        c.g.ny = prm.n[1];
+        c.g.nz = prm.n[2];
+        c.g.bcx = prm.bc[0];
+        c.g.bcy = prm.bc[1];
+        c.g.bcz = prm.dim == 3 ? prm.bc[2] : mplb::BC_PER;
+        c.g.np = L.np;
+        c.ph = ph;
+        c.block = block;
+        c.stream = stream;
+        c.p.Fin = F(in);
+        c.p.Gin = G(in);
+        c.p.Fout = F(1 - in);
+        c.p.Gout = G(1 - in);
+        c.p.phi = base + L.phi;
+        c.p.fp_in = static_cast<const float *>(at(L.fp[in]));
+        c.p.fr_in = static_cast<const float *>(at(L.fr[in]));
+        c.p.gp_in = static_cast<const float *>(at(L.gp[in]));
+        c.p.fp_out = static_cast<float *>(at(L.fp[1 - in]));
+        c.p.fr_out = static_cast<float *>(at(L.fr[1 - in]));
+        c.p.gp_out = static_cast<float *>(at(L.gp[1 - in]));
+        return c;
+    }
+
+    // Context that writes (in place) into buffer k.
+    mplb::Ctx ctx_write(int k) const
+    {
+        mplb::Ctx c = ctx(1 - k);
+        return c;
+    }
+};
+
+extern "C" {
+
+int32_t mplb_version(void) { return MPLB_VERSION; }
+
+const char *mplb_arch(void) { return "gfx950"; }
+
+const char *mplb_last_error(void) { return g_err.c_str(); }
+
+size_t mplb_state_bytes(const mplb_params *p)
+{
+    std::string why;
+    if (!validate(p, why)) {
+        g_err = why;
+        return 0;
+    }
+    return make_layout(p).total;
+}
+
+int mplb_create(const mplb_params *p, void *dev_arena, size_t arena_bytes, void *hip_stream,
+                mplb_solver **out)
+{
+    std::string why;
+    if (!out) return fail(MPLB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!validate(p, why)) return fail(MPLB_EINVAL, why);
+    if (!dev_arena) return fail(MPLB_EINVAL, "arena is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_arena) % ALIGN)
+        return fail(MPLB_EINVAL, "arena must be 256-byte aligned");
+    const Layout L = make_layout(p);
+    if (arena_bytes < L.total)
+        return fail(MPLB_ENOMEM, "arena holds " + std::to_string(arena_bytes) + " bytes, " +
+                                     std::to_string(L.total) + " needed");
+    mplb_solver *s = new (std::nothrow) mplb_solver();
+    if (!s) return fail(MPLB_ENOMEM, "host allocation failed");
+    s->prm = *p;
+    s->L = L;
+    s->base = static_cast<char *>(dev_arena);
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    s->cur = 0;
+    s->steps = 0;
+    s->ready = false;
+    s->attached = false;
+    s->block = default_block(p);
+    s->ph = make_phys(p);
+    *out = s;
+    return MPLB_OK;
+}
+
+void mplb_destroy(mplb_solver *s) { delete s; }
+
+int mplb_tune_block(mplb_solver *s, int32_t steps, const int32_t *candidates, int32_t ncand,
+                    int32_t best[3], double *best_ms_per_step)
+{
+    static const int32_t builtin3[] = {64, 4, 1, 64, 2, 2, 64, 1, 4, 32, 8, 1, 32, 4, 2,
+                                       128, 2, 1, 128, 1, 2, 256, 1, 1, 64, 2, 1, 32, 2, 2};
+    static const int32_t builtin2[] = {64, 4, 1, 32, 8, 1, 128, 2, 1, 256, 1, 1, 64, 2, 1,
+                                       16, 16, 1, 128, 1, 1};
+    if (!s || !best || !best_ms_per_step) return fail(MPLB_EINVAL, "solver and outputs are required");
+    if (steps < 1) return fail(MPLB_EINVAL, "steps must be >= 1");
+    if (!candidates) {
+        candidates = s->prm.dim == 3 ? builtin3 : builtin2;
+        ncand = s->prm.dim == 3 ? int32_t(sizeof(builtin3) / 12) : int32_t(sizeof(builtin2) / 12);
+    }
+    const dim3 keep = s->block;
+    double best_ms = 1e300;
+    for (int i = 0; i < ncand; ++i) {
+        const int32_t *c = candidates + 3 * i;
+        if (s->prm.dim == 2 && c[2] != 1) continue;
+        if (mplb_set_block(s, c[0], c[1], c[2]) != MPLB_OK) continue;
+        double a = 0, b = 0;
+        int rc = mplb_step_timed(s, 2, &a, &b);
+        if (rc == MPLB_OK) rc = mplb_step_timed(s, steps, &a, &b);
+        if (rc != MPLB_OK) {
+            s->block = keep;
+            return rc;
+        }
+        const double ms = (a + b) / steps;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best[0] = c[0];
+            best[1] = c[1];
+            best[2] = c[2];
+        }
+    }
+    if (best_ms == 1e300) {
+        s->block = keep;
+        return fail(MPLB_EINVAL, "no valid candidate block shape");
+    }
+    s->block = dim3(best[0], best[1], best[2]);
+    *best_ms_per_step = best_ms;
+    return MPLB_OK;
+}
+
+int mplb_set_block(mplb_solver *s, int32_t bx, int32_t by, int32_t bz)
+{
+    if (!s) return fail(MPLB_EINVAL, "solver is NULL");
+    if (bx == 0 && by == 0 && bz == 0) {
+        s->block = default_block(&s->prm);
+        return MPLB_OK;
+    }
+    if (bx < 1 || by < 1 || bz < 1 || (long long)bx * by * bz > 256)
+        return fail(MPLB_EINVAL, "block must have between 1 and 256 threads");
+    if (s->prm.dim == 2 && bz != 1) return fail(MPLB_EINVAL, "bz must be 1 in 2-D");
+    s->block = dim3(bx, by, bz);
+    return MPLB_OK;
+}
+
+int mplb_init(mplb_solver *s, const double *phi, const double *u, const double *p)
+{
+    if (!s || !phi || !u) return fail(MPLB_EINVAL, "solver, phi and u are required");
+    const long long N = s->L.N;
+    const size_t nb = N * sizeof(double);
+    // inputs staged as FP64 in buffer 1: phi, u (dim components), p
+    double *st = s->staging(1);
+    double *dphi = st, *du = st + N, *dp = st + (1 + s->prm.dim) * N;
+    HIPCHK(hipMemcpyAsync(dphi, phi, nb, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(du, u, nb * s->prm.dim, hipMemcpyHostToDevice, s->stream));
+    if (p)
+        HIPCHK(hipMemcpyAsync(dp, p, nb, hipMemcpyHostToDevice, s->stream));
+    else
+        HIPCHK(hipMemsetAsync(dp, 0, nb, s->stream));
+    const mplb::Ctx c = s->ctx_write(0);
+    if (c.p.fp_out || c.p.gp_out) HIPCHK(mplb::launch_set_refs(c, dphi, dp));
+    HIPCHK(mplb::launch_init(c, dphi, du, dp));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->cur = 0;
+    s->steps = 0;
+    s->ready = true;
+    return MPLB_OK;
+}
+
+int mplb_step(mplb_solver *s, int64_t nsteps)
+{
+    if (!s) return fail(MPLB_EINVAL, "solver is NULL");
+    if (nsteps < 0) return fail(MPLB_EINVAL, "nsteps must be >= 0");
+    if (!s->ready) return fail(MPLB_ESTATE, "mplb_init has not been called");
+    if (s->attached) return fail(MPLB_ESTATE, "solver is attached to a batch");
+    for (int64_t i = 0; i < nsteps; ++i) {
+        const mplb::Ctx c = s->ctx(s->cur);
+        HIPCHK(mplb::launch_phi(c));
+        HIPCHK(mplb::launch_collide(c));
+        s->cur ^= 1;
+        s->steps++;
+    }
+    return MPLB_OK;
+}
+
+int mplb_step_timed(mplb_solver *s, int64_t nsteps, double *ms_phi, double *ms_collide)
+{
+    if (!s || !ms_phi || !ms_collide) return fail(MPLB_EINVAL, "solver and outputs are required");
+    if (nsteps < 0) return fail(MPLB_EINVAL, "nsteps must be >= 0");
+    if (!s->ready) return fail(MPLB_ESTATE, "mplb_init has not been called");
+    constexpr int BATCH = 64;
+    hipEvent_t ev[2 * BATCH + 1];
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    double tphi = 0.0, tcol = 0.0;
+    int rc = MPLB_OK;
+    for (int64_t done = 0; done < nsteps && rc == MPLB_OK;) {
+        const int k = int(nsteps - done < BATCH ? nsteps - done : BATCH);
+        hipError_t e = hipEventRecord(ev[0], s->stream);
+        for (int i = 0; i < k && e == hipSuccess; ++i) {
+            const mplb::Ctx c = s->ctx(s->cur);
+            e = mplb::launch_phi(c);
+            if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 1], s->stream);
+            if (e == hipSuccess) e = mplb::launch_collide(c);
+            if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 2], s->stream);
+            s->cur ^= 1;
+            s->steps++;
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(ev[2 * k]);
+        for (int i = 0; i < k && e == hipSuccess; ++i) {
+            float a = 0.f, b = 0.f;
+            e = hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]);
+            tphi += a;
+            tcol += b;
+        }
+        if (e != hipSuccess) rc = fail(MPLB_EDEVICE, std::string("timed step: ") + hipGetErrorString(e));
+        done += k;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    *ms_phi = tphi;
+    *ms_collide = tcol;
+    return rc;
+}
+
+int mplb_sync(mplb_solver *s)
+{
+    if (!s) return fail(MPLB_EINVAL, "solver is NULL");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MPLB_OK;
+}
+
+int64_t mplb_steps_done(const mplb_solver *s) { return s ? s->steps : -1; }
+
+int mplb_read(mplb_solver *s, int32_t field, double *host_out)
+{
+    if (!s || !host_out) return fail(MPLB_EINVAL, "solver and host_out are required");
+    if (field < MPLB_FIELD_PHI || field > MPLB_FIELD_P) return fail(MPLB_EINVAL, "unknown field");
+    if (!s->ready) return fail(MPLB_ESTATE, "mplb_init has not been called");
+    if (s->prm.dim == 2 && field == MPLB_FIELD_UZ) {
+        std::memset(host_out, 0, s->L.N * sizeof(double));
+        return MPLB_OK;
+    }
+    const mplb::Ctx c = s->ctx(s->cur);
+    double *st = s->staging(1 - s->cur);
+    HIPCHK(mplb::launch_phi(c));
+    HIPCHK(mplb::launch_field(c, field, st));
+    HIPCHK(hipMemcpyAsync(host_out, st, s->L.N * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MPLB_OK;
+}
+
+int mplb_reduce(mplb_solver *s, double out[5])
+{
+    if (!s || !out) return fail(MPLB_EINVAL, "solver and out are required");
+    if (!s->ready) return fail(MPLB_ESTATE, "mplb_init has not been called");
+    const mplb::Ctx c = s->ctx(s->cur);
+    double *partials = reinterpret_cast<double *>(s->base + s->L.partials);
+    double *res = reinterpret_cast<double *>(s->base + s->L.result);
+    double host[8];
+    HIPCHK(mplb::launch_phi(c));
+    HIPCHK(mplb::launch_reduce(c, partials, res));
+    HIPCHK(hipMemcpyAsync(host, res, 6 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (int k = 0; k < 5; ++k) out[k] = host[k];
+    if (host[5] != 0.0) return fail(MPLB_EUNSTABLE, "non-finite values in the state");
+    return MPLB_OK;
+}
+
+int mplb_get_populations(mplb_solver *s, int32_t which, double *host_out)
+{
+    if (!s || !host_out) return fail(MPLB_EINVAL, "solver and host_out are required");
+    if (which != 0 && which != 1) return fail(MPLB_EINVAL, "which must be 0 (f') or 1 (g)");
+    if (!s->ready) return fail(MPLB_ESTATE, "mplb_init has not been called");
+    const long long N = s->L.N;
+    const int chunk = int(s->L.staging_bytes / (N * sizeof(double)));
+    const mplb::Ctx c = s->ctx(s->cur);
+    double *st = s->staging(1 - s->cur);
+    for (int a0 = 0; a0 < s->L.Q; a0 += chunk) {
+        const int a1 = a0 + chunk < s->L.Q ? a0 + chunk : s->L.Q;
+        HIPCHK(mplb::launch_get_pop(c, which, a0, a1, st));
+        HIPCHK(hipMemcpyAsync(host_out + (long long)a0 * N, st, (a1 - a0) * N * sizeof(double),
+                              hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    return MPLB_OK;
+}
+
+int mplb_set_populations(mplb_solver *s, int32_t which, const double *host_in)
+{
+    if (!s || !host_in) return fail(MPLB_EINVAL, "solver and host_in are required");
+    if (which != 0 && which != 1) return fail(MPLB_EINVAL, "which must be 0 (f') or 1 (g)");
+    const bool shifted = which == 0 ? s->L.sF == 2 : s->L.sG == 2;
+    if (shifted && !s->ready)
+        return fail(MPLB_ESTATE, "FP16-shifted sets keep the shift/scale of the current state: "
+                                 "call mplb_init first");
+    const long long N = s->L.N;
+    const int chunk = int(s->L.staging_bytes / (N * sizeof(double)));
+    // write in place into the current buffer; stage through the idle one
+    const mplb::Ctx c = s->ctx_write(s->cur);
+    double *st = s->staging(1 - s->cur);
+    for (int a0 = 0; a0 < s->L.Q; a0 += chunk) {
+        const int a1 = a0 + chunk < s->L.Q ? a0 + chunk : s->L.Q;
+        HIPCHK(hipMemcpyAsync(st, host_in + (long long)a0 * N, (a1 - a0) * N * sizeof(double),
+                              hipMemcpyHostToDevice, s->stream));
+        HIPCHK(mplb::launch_set_pop(c, which, a0, a1, st));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    s->ready = true;
+    s->steps = 0;
+    return MPLB_OK;
+}
+
+
+}  // extern "C"
+
+/* ------------------------------------------------------------------ batches */
+
+struct mplb_batch {
+    int dim, storage, capacity;
+    long long max_tiles;
+    hipStream_t stream;
+    mplb::BatchDom *d_doms;
+    mplb::BatchTile *d_tiles;
+    int *d_ntiles;
+    long long *d_tbase;
+    std::vector<mplb_solver *> slot;
+    std::vector<mplb::BatchDom> doms;
+    std::vector<mplb::BatchTile> tiles;
+    int ntiles_host;
+    dim3 block;
+    int grid;
+    int chunk;
+    long long t;  // batch steps taken
+    hipGraphExec_t exec;
+    bool have_graph;
+};
+
+namespace {
+
+size_t table_layout(int32_t capacity, int64_t max_tiles, size_t *o_doms, size_t *o_tiles,
+                    size_t *o_nt, size_t *o_tb)
+{
+    size_t off = 0;
+    *o_doms = off;
+    off += up(sizeof(mplb::BatchDom) * capacity, ALIGN);
+    *o_tiles = off;
+    off += up(sizeof(mplb::BatchTile) * max_tiles, ALIGN);
+    *o_nt = off;
+    off += ALIGN;
+    *o_tb = off;
+    off += ALIGN;
+    return off;
+}
+
+void drop_graph(mplb_batch *b)
+{
+    if (b->have_graph) (void)hipGraphExecDestroy(b->exec);
+    b->have_graph = false;
+}
+
+// Rebuild the tile list from the attached solvers and upload it with the
+// domain table; synchronises the stream so the host copies can be reused.
+int upload_tables(mplb_batch *b)
+{
+    b->tiles.clear();
+    const int bx = b->block.x, by = b->block.y, bz = b->block.z;
+    for (int i = 0; i < b->capacity; ++i) {
+        const mplb_solver *s = b->slot[i];
+        if (!s) continue;
+        for (int z0 = 0; z0 < s->prm.n[2]; z0 += bz)
+            for (int y0 = 0; y0 < s->prm.n[1]; y0 += by)
+                for (int x0 = 0; x0 < s->prm.n[0]; x0 += bx) {
+                    if ((long long)b->tiles.size() >= b->max_tiles)
+                        return fail(MPLB_ENOMEM, "batch tile list is full");
+                    b->tiles.push_back(mplb::BatchTile{i, x0, y0, z0});
+                }
+    }
+    b->ntiles_host = int(b->tiles.size());
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_doms, b->doms.data(), sizeof(mplb::BatchDom) * b->capacity,
+                          hipMemcpyHostToDevice, b->stream));
+    if (b->ntiles_host)
+        HIPCHK(hipMemcpyAsync(b->d_tiles, b->tiles.data(), sizeof(mplb::BatchTile) * b->ntiles_host,
+                              hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_ntiles, &b->ntiles_host, sizeof(int), hipMemcpyHostToDevice,
+                          b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return MPLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mplb_batch_table_bytes(int32_t capacity, int64_t max_tiles)
+{
+    if (capacity < 1 || max_tiles < 1) return 0;
+    size_t a, b, c, d;
+    return table_layout(capacity, max_tiles, &a, &b, &c, &d);
+}
+
+int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t max_tiles,
+                      void *dev_table, size_t table_bytes, void *hip_stream, mplb_batch **out)
+{
+    if (!out) return fail(MPLB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (dim != 2 && dim != 3) return fail(MPLB_EINVAL, "dim must be 2 or 3");
+    if (storage < MPLB_STORE_FP64 || storage > MPLB_STORE_FP16S_ALL)
+        return fail(MPLB_EINVAL, "unknown storage format");
+    if (capacity < 1 || max_tiles < 1 || max_tiles > 0x7fffffff)
+        return fail(MPLB_EINVAL, "capacity and max_tiles must be >= 1");
+    if (!dev_table || reinterpret_cast<uintptr_t>(dev_table) % ALIGN)
+        return fail(MPLB_EINVAL, "table memory must be non-NULL and 256-byte aligned");
+    size_t od, ot, on, ob;
+    const size_t need = table_layout(capacity, max_tiles, &od, &ot, &on, &ob);
+    if (table_bytes < need) return fail(MPLB_ENOMEM, "batch table memory too small");
+    mplb_batch *b = new (std::nothrow) mplb_batch();
+    if (!b) return fail(MPLB_ENOMEM, "host allocation failed");
+    char *base = static_cast<char *>(dev_table);
+    b->dim = dim;
+    b->storage = storage;
+    b->capacity = capacity;
+    b->max_tiles = max_tiles;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->d_doms = reinterpret_cast<mplb::BatchDom *>(base + od);
+    b->d_tiles = reinterpret_cast<mplb::BatchTile *>(base + ot);
+    b->d_ntiles = reinterpret_cast<int *>(base + on);
+    b->d_tbase = reinterpret_cast<long long *>(base + ob);
+    b->slot.assign(capacity, nullptr);
+    b->doms.assign(capacity, mplb::BatchDom{});
+    b->ntiles_host = 0;
+    b->block = dim3(64, 4, 1);
+    b->grid = 2048;
+    b->chunk = 16;
+    b->t = 0;
+    b->have_graph = false;
+    const int rc = upload_tables(b);
+    if (rc != MPLB_OK) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return MPLB_OK;
+}
+
+int mplb_batch_set_block(mplb_batch *b, int32_t bx, int32_t by, int32_t bz)
+{
+    if (!b) return fail(MPLB_EINVAL, "batch is NULL");
+    if (bx < 1 || by < 1 || bz < 1 || (long long)bx * by * bz > 256)
+        return fail(MPLB_EINVAL, "block must have between 1 and 256 threads");
+    if (b->dim == 2 && bz != 1) return fail(MPLB_EINVAL, "bz must be 1 in 2-D");
+    b->block = dim3(bx, by, bz);
+    drop_graph(b);
+    return upload_tables(b);
+}
+
+int mplb_batch_set_graph_chunk(mplb_batch *b, int32_t chunk)
+{
+    if (!b) return fail(MPLB_EINVAL, "batch is NULL");
+    if (chunk < 0 || chunk > 4096) return fail(MPLB_EINVAL, "chunk must be in [0, 4096]");
+    b->chunk = chunk;
+    drop_graph(b);
+    return MPLB_OK;
+}
+
+int mplb_batch_attach(mplb_batch *b, mplb_solver *s, int64_t nsteps, int32_t *slot)
+{
+    if (!b || !s || !slot) return fail(MPLB_EINVAL, "batch, solver and slot are required");
+    if (nsteps < 0) return fail(MPLB_EINVAL, "nsteps must be >= 0");
+    if (s->prm.dim != b->dim || s->prm.storage != b->storage)
+        return fail(MPLB_EINVAL, "solver dimension/storage differ from the batch's");
+    if (s->stream != b->stream) return fail(MPLB_EINVAL, "solver and batch streams differ");
+    if (!s->ready) return fail(MPLB_ESTATE, "solver is not initialised");
+    if (s->attached) return fail(MPLB_ESTATE, "solver is already attached");
+    int k = -1;
+    for (int i = 0; i < b->capacity; ++i)
+        if (!b->slot[i]) {
+            k = i;
+            break;
+        }
+    if (k < 0) return fail(MPLB_ENOMEM, "no free batch slot");
+    mplb::BatchDom d{};
+    const mplb::Ctx c = s->ctx(0);
+    d.g = c.g;
+    d.ph = s->ph;
+    for (int j = 0; j < 2; ++j) {
+        d.F[j] = s->F(j);
+        d.G[j] = s->G(j);
+        d.fp[j] = static_cast<float *>(s->at(s->L.fp[j]));
+        d.fr[j] = static_cast<float *>(s->at(s->L.fr[j]));
+        d.gp[j] = static_cast<float *>(s->at(s->L.gp[j]));
+    }
+    d.phi = s->base + s->L.phi;
+    // input buffer at batch step t is (t - first) & 1; at t = b->t it is s->cur
+    d.first = b->t - s->cur;
+    d.last = b->t + nsteps;
+    b->slot[k] = s;
+    b->doms[k] = d;
+    s->attached = true;
+    const int rc = upload_tables(b);
+    if (rc != MPLB_OK) {
+        b->slot[k] = nullptr;
+        b->doms[k] = mplb::BatchDom{};
+        s->attached = false;
+        (void)upload_tables(b);
+        return rc;
+    }
+    *slot = k;
+    return MPLB_OK;
+}
+
+int mplb_batch_detach(mplb_batch *b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->capacity || !b->slot[slot])
+        return fail(MPLB_EINVAL, "no solver in that slot");
+    b->slot[slot]->attached = false;
+    b->slot[slot] = nullptr;
+    b->doms[slot] = mplb::BatchDom{};
+    return upload_tables(b);
+}
+
+int mplb_batch_remaining(const mplb_batch *b, int32_t slot, int64_t *remaining)
+{
+    if (!b || !remaining || slot < 0 || slot >= b->capacity || !b->slot[slot])
+        return fail(MPLB_EINVAL, "no solver in that slot");
+    const long long r = b->doms[slot].last - b->t;
+    *remaining = r > 0 ? r : 0;
+    return MPLB_OK;
+}
+
+int64_t mplb_batch_steps_done(const mplb_batch *b) { return b ? b->t : -1; }
+
+int mplb_batch_step(mplb_batch *b, int64_t nsteps)
+{
+    if (!b) return fail(MPLB_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(MPLB_EINVAL, "nsteps must be >= 0");
+    const long long t0 = b->t;
+    long long done = 0;
+    while (done < nsteps) {
+        const long long left = nsteps - done;
+        HIPCHK(mplb::launch_set_i64(b->d_tbase, b->t, b->stream));
+        if (b->chunk > 0 && left >= b->chunk) {
+            if (!b->have_graph) {
+                hipGraph_t graph;
+                HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+                hipError_t e = hipSuccess;
+                for (int k = 0; k < b->chunk && e == hipSuccess; ++k)
+                    e = mplb::launch_batch_step(b->dim, b->storage, b->d_doms, b->d_tiles,
+                                                b->d_ntiles, b->d_tbase, k, b->block, b->grid,
+                                                b->stream);
+                hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+                if (e != hipSuccess || e2 != hipSuccess)
+                    return fail(MPLB_EDEVICE, std::string("graph capture: ") +
+                                                  hipGetErrorString(e != hipSuccess ? e : e2));
+                e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e != hipSuccess)
+                    return fail(MPLB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+                b->have_graph = true;
+            }
+            HIPCHK(hipGraphLaunch(b->exec, b->stream));
+            b->t += b->chunk;
+            done += b->chunk;
+        } else {
+            HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->d_doms, b->d_tiles, b->d_ntiles,
+                                           b->d_tbase, 0, b->block, b->grid, b->stream));
+            b->t += 1;
+            done += 1;
+        }
+    }
+    // host bookkeeping: each attached solver advanced by the overlap of its
+    // window with [t0, t); windows open at or before t0
+    for (int i = 0; i < b->capacity; ++i) {
+        mplb_solver *s = b->slot[i];
+        if (!s) continue;
+        const long long lo = t0;
+        const long long hi = b->t < b->doms[i].last ? b->t : b->doms[i].last;
+        const long long adv = hi > lo ? hi - lo : 0;
+        s->steps += adv;
+        s->cur = int((s->cur + adv) & 1);
+    }
+    return MPLB_OK;
+}
+
+void mplb_batch_destroy(mplb_batch *b)
+{
+    if (!b) return;
+    for (auto *s : b->slot)
+        if (s) s->attached = false;
+    drop_graph(b);
+    delete b;
+}
+
+}  // extern "C"

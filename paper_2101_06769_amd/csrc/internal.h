@@ -1,0 +1,95 @@
+// Host-side interface between the C ABI (api.cpp) and the kernel launchers
+// (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+
+namespace mplb {
+
+enum { ST_FP64 = 0, ST_FP32 = 1, ST_FP16S = 2, ST_FP16S_ALL = 3 };
+
+// Physical parameters in the form the kernels use (double on the host,
+// converted to the arithmetic type at launch).
+struct PhysD {
+    double rho_l, drho;    // rho = rho_l + drho phi
+    double nu_l, dnu;      // nu = nu_l + dnu phi            (visc_interp 0)
+    double rnu_l, drnu;    // nu = (rnu_l + drnu phi) / rho  (visc_interp 1)
+    double beta, kappa;    // chemical potential coefficients
+    double gx, gy, gz;     // body-force acceleration
+    double inv_tpb;        // 1 / taubar_phi
+    double src_pre;        // 1 - 1/(2 taubar_phi)
+    double four_W;         // 4 / W
+    int visc_interp;
+    int collision;         // 0 cumulant, 1 SRT
+};
+
+// Device buffers one launch works on.  "in" buffers hold the post-collision
+// state of the previous step (pre-collision values are pulled from them);
+// "out" buffers receive the new post-collision state.
+struct Ptrs {
+    const void *Fin;
+    void *Fout;
+    const void *Gin;
+    void *Gout;
+    void *phi;            // order parameter of the current time level
+    // FP16-shifted storage: per-cell shift and scale of the encoded values
+    const float *fp_in, *fr_in;   // f': pressure shift, rho cs^2 scale
+    float *fp_out, *fr_out;
+    const float *gp_in;           // g: phi shift
+    float *gp_out;
+};
+
+struct Ctx {
+    int dim;
+    int storage;
+    Geom g;
+    PhysD ph;
+    dim3 block;
+    hipStream_t stream;
+    Ptrs p;
+};
+
+hipError_t launch_phi(const Ctx &c);
+hipError_t launch_collide(const Ctx &c);
+// Equilibrium initial state from device FP64 fields (phi[N], u[dim][N], p[N])
+// written into the Fout/Gout buffers in pull layout.
+hipError_t launch_init(const Ctx &c, const double *phi, const double *u, const double *pr);
+// Pre-collision populations a0..a1-1 of set `which` (0 f', 1 g) from the
+// Fin/Gin buffers into dst[(a-a0)][N] (FP64).
+hipError_t launch_get_pop(const Ctx &c, int which, int a0, int a1, double *dst);
+// The inverse: src[(a-a0)][N] into the Fout/Gout buffers in pull layout.
+hipError_t launch_set_pop(const Ctx &c, int which, int a0, int a1, const double *src);
+// Per-cell shift/scale of FP16-shifted formats (the *_out arrays) from FP64
+// order-parameter and pressure fields.
+hipError_t launch_set_refs(const Ctx &c, const double *phi, const double *pr);
+// One macroscopic field of the state held in Fin/Gin (phi must be current).
+hipError_t launch_field(const Ctx &c, int field, double *dst);
+// Deterministic FP64 reduction: partials (at least reduce_blocks() x 8
+// doubles), out[8] = {sum phi, sum rho ux, uy, uz, max|u|, nonfinite count}.
+hipError_t launch_reduce(const Ctx &c, double *partials, double *out);
+int reduce_blocks(const Ctx &c);
+
+// One domain of a batch, as the batched kernels read it from device memory.
+struct BatchDom {
+    Geom g;
+    PhysD ph;
+    void *F[2], *G[2], *phi;
+    float *fp[2], *fr[2], *gp[2];
+    long long first, last;  // active for batch steps first <= t < last
+};
+
+// A tile of a batch: domain index and the tile's origin cell.
+struct BatchTile {
+    int dom, x0, y0, z0;
+};
+
+// One step of every active domain: persistent blocks stride over the tile
+// list (*ntiles entries); the batch step index is *tbase + step_off.
+hipError_t launch_batch_step(int dim, int storage, const BatchDom *doms, const BatchTile *tiles,
+                             const int *ntiles, const long long *tbase, int step_off, dim3 block,
+                             int grid, hipStream_t stream);
+hipError_t launch_set_i64(long long *ptr, long long v, hipStream_t stream);
+
+}  // namespace mplb

@@ -1,0 +1,912 @@
+// HIP kernels (gfx950) for one time step of the multiphase lattice Boltzmann
+// method of arXiv 2101.06769: conservative Allen-Cahn phase-field populations
+// (Sec. 2.2) coupled to pressure-based flow populations under the cumulant
+// collision operator (Sec. 2.3).
+//
+// A step is two launches over the lattice:
+//   k_phi      phi(x) = sum_a g_a(x), the g_a pulled from the post-collision
+//              buffer of the previous step (Sec. 2.2, zeroth moment);
+//   k_collide  per cell: isotropic gradient and Laplacian of phi (Sec. 2.2),
+//              closure (density, chemical potential, forces, normal), flow
+//              collision, phase-field collision, post-collision values
+//              stored at the cell (pull streaming: the next step gathers).
+//
+// Flow collision.  All cumulant rates other than the viscous ones are unity
+// (Sec. 2.3), so every post-collision cumulant above second order is zero and
+// the post-collision set is determined by the conserved moments and the six
+// (three in 2-D) relaxed second-order central moments.  The kernel therefore
+// streams the Q pulled populations once, accumulating ten raw moments, adds
+// the moments of the source Xi in closed form, relaxes in moment space, and
+// rebuilds the populations from the central moments of the relaxed set
+// (higher orders are products of second-order ones: the Gaussian moment
+// closure implied by zero higher cumulants) with three 3-point sweeps.  The
+// unit-mass set h = f^p - w (P - 1) is the one transformed; w (P - 1) passes
+// through the collision unchanged.
+//
+// The work is memory-bound (about 440 B/cell/step in FP32 for D3Q27 at a few
+// kflop), so the kernels are written for coalesced structure-of-arrays access:
+// one thread per cell, x fastest across a 64-wide wavefront, each direction a
+// separate plane.
+#include <hip/hip_fp16.h>
+
+#include "internal.h"
+
+namespace mplb {
+
+// ------------------------------------------------------------------ storage
+template <typename Raw>
+struct Plain {
+    using raw = Raw;
+    static constexpr bool shifted = false;
+};
+struct Half16 {
+    using raw = __half;
+    static constexpr bool shifted = true;
+};
+
+template <class SF, class SG, typename TT>
+struct Pol {
+    using F = SF;
+    using G = SG;
+    using T = TT;
+};
+using P64 = Pol<Plain<double>, Plain<double>, double>;
+using P32 = Pol<Plain<float>, Plain<float>, float>;
+using P16 = Pol<Half16, Plain<float>, float>;
+using P16A = Pol<Half16, Half16, float>;
+
+// Value of direction plane `dir` at `cell`.  Shifted FP16 values decode as
+// w (shift + scale q) with the shift/scale of the cell that stored them
+// (scale 1 when sc is null).
+template <int D, class S, typename T>
+__device__ __forceinline__ T load_pop(const void *base, long long np, int dir, int cell, int a,
+                                      const float *sh, const float *sc)
+{
+    if constexpr (S::shifted) {
+        const float q = __half2float(static_cast<const __half *>(base)[(long long)dir * np + cell]);
+        const float w = weight<D, float>(a);
+        return T(w * (sh[cell] + (sc ? sc[cell] : 1.0f) * q));
+    } else {
+        return T(static_cast<const typename S::raw *>(base)[(long long)dir * np + cell]);
+    }
+}
+
+// Store dev + w shift (plain) or dev / (w scale) (shifted).
+template <int D, class S, typename T>
+__device__ __forceinline__ void store_dev(void *base, long long np, int a, int cell, T dev, T shift,
+                                          T scale)
+{
+    if constexpr (S::shifted) {
+        const float w = weight<D, float>(a);
+        static_cast<__half *>(base)[(long long)a * np + cell] =
+            __float2half(float(dev) / (w * float(scale)));
+    } else {
+        static_cast<typename S::raw *>(base)[(long long)a * np + cell] =
+            typename S::raw(dev + weight<D, T>(a) * shift);
+    }
+}
+
+// Parameters in the arithmetic type.
+template <typename T>
+struct Phys {
+    T rho_l, drho, nu_l, dnu, rnu_l, drnu, beta, kappa, gx, gy, gz, inv_tpb, src_pre, four_W;
+    int visc_interp, collision;
+};
+
+template <typename T>
+__host__ __device__ static Phys<T> to_phys(const PhysD &d)
+{
+    Phys<T> p;
+    p.rho_l = T(d.rho_l);
+    p.drho = T(d.drho);
+    p.nu_l = T(d.nu_l);
+    p.dnu = T(d.dnu);
+    p.rnu_l = T(d.rnu_l);
+    p.drnu = T(d.drnu);
+    p.beta = T(d.beta);
+    p.kappa = T(d.kappa);
+    p.gx = T(d.gx);
+    p.gy = T(d.gy);
+    p.gz = T(d.gz);
+    p.inv_tpb = T(d.inv_tpb);
+    p.src_pre = T(d.src_pre);
+    p.four_W = T(d.four_W);
+    p.visc_interp = d.visc_interp;
+    p.collision = d.collision;
+    return p;
+}
+
+// ------------------------------------------------------------- cell state
+template <typename T>
+struct Cell {
+    T phi, gx, gy, gz, lap;
+    T rho, irho, drx, dry, drz, mu, Fx, Fy, Fz, omega;
+    T S0, Sx, Sy, Sz, Sxx, Syy, Szz, Sxy, Sxz, Syz;
+    T ux, uy, uz, pstar, U;
+};
+
+// grad(phi) = (1/cs^2) sum_a w_a c_a phi(x + c_a);
+// lap(phi) = (2/cs^2) sum_a w_a [phi(x + c_a) - phi(x)]   (Sec. 2.2)
+// Summed over pairs of opposite directions, w (phi(x+c) - phi(x-c)) and
+// w (phi(x+c) + phi(x-c) - 2 phi(x)), so that uniform and mirror-symmetric
+// fields give exactly zero gradient components.
+template <int D, typename T>
+__device__ __forceinline__ void stencil(const Geom &g, const T *__restrict__ phi, int x, int y,
+                                        int z, Cell<T> &c)
+{
+    constexpr int Q = Lat<D>::Q;
+    const T p0 = phi[cell_of(g, x, y, z)];
+    T gx = 0, gy = 0, gz = 0, lap = 0;
+#pragma unroll
+    for (int a = Q / 2 + 1; a < Q; ++a) {
+        const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
+        const int xp = cx ? stencil_coord(x + cx, g.nx, g.bcx) : x;
+        const int yp = cy ? stencil_coord(y + cy, g.ny, g.bcy) : y;
+        const int zp = (D == 3 && cz) ? stencil_coord(z + cz, g.nz, g.bcz) : z;
+        const int xm = cx ? stencil_coord(x - cx, g.nx, g.bcx) : x;
+        const int ym = cy ? stencil_coord(y - cy, g.ny, g.bcy) : y;
+        const int zm = (D == 3 && cz) ? stencil_coord(z - cz, g.nz, g.bcz) : z;
+        const T pp = phi[cell_of(g, xp, yp, zp)];
+        const T pm = phi[cell_of(g, xm, ym, zm)];
+        const T w = weight<D, T>(a);
+        const T d = w * (pp - pm);
+        if (cx) gx += T(cx) * d;
+        if (cy) gy += T(cy) * d;
+        if (cz) gz += T(cz) * d;
+        lap += w * ((pp - p0) + (pm - p0));
+    }
+    c.phi = p0;
+    c.gx = T(3) * gx;
+    c.gy = T(3) * gy;
+    c.gz = T(3) * gz;
+    c.lap = T(6) * lap;
+}
+
+// Density and its gradient, chemical potential, forces, relaxation rate
+// (Sec. 2.1, 2.3).
+template <int D, typename T>
+__device__ __forceinline__ void closure(const Phys<T> &ph, Cell<T> &c)
+{
+    c.rho = ph.rho_l + ph.drho * c.phi;
+    c.irho = T(1) / c.rho;
+    c.drx = ph.drho * c.gx;
+    c.dry = ph.drho * c.gy;
+    c.drz = ph.drho * c.gz;
+    c.mu = T(2) * ph.beta * c.phi * (c.phi - T(1)) * (T(2) * c.phi - T(1)) - ph.kappa * c.lap;
+    c.Fx = c.mu * c.gx + c.rho * ph.gx;
+    c.Fy = c.mu * c.gy + c.rho * ph.gy;
+    c.Fz = D == 3 ? c.mu * c.gz + c.rho * ph.gz : T(0);
+    const T nu = ph.visc_interp ? (ph.rnu_l + ph.drnu * c.phi) * c.irho : ph.nu_l + ph.dnu * c.phi;
+    c.omega = T(1) / (T(3) * nu + T(0.5));
+}
+
+// Raw moments of the pulled flow populations (orders 0..2).
+template <int D, class P>
+__device__ __forceinline__ void flow_moments(const Geom &g, const Ptrs &p, int x, int y, int z,
+                                             Cell<typename P::T> &c)
+{
+    using T = typename P::T;
+    constexpr int Q = Lat<D>::Q;
+    T S0 = 0, Sx = 0, Sy = 0, Sz = 0, Sxx = 0, Syy = 0, Szz = 0, Sxy = 0, Sxz = 0, Syz = 0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
+        int dir, cell;
+        pull_src<D>(g, x, y, z, a, &dir, &cell);
+        const T v = load_pop<D, typename P::F, T>(p.Fin, g.np, dir, cell, a, p.fp_in, p.fr_in);
+        S0 += v;
+        if (cx) { Sx += T(cx) * v; Sxx += v; }
+        if (cy) { Sy += T(cy) * v; Syy += v; }
+        if (cz) { Sz += T(cz) * v; Szz += v; }
+        if (cx && cy) Sxy += T(cx * cy) * v;
+        if (cx && cz) Sxz += T(cx * cz) * v;
+        if (cy && cz) Syz += T(cy * cz) * v;
+    }
+    c.S0 = S0; c.Sx = Sx; c.Sy = Sy; c.Sz = Sz;
+    c.Sxx = Sxx; c.Syy = Syy; c.Szz = Szz; c.Sxy = Sxy; c.Sxz = Sxz; c.Syz = Syz;
+}
+
+// Velocity: first moment of f^p = f'/(rho cs^2) + Xi/(2 rho cs^2), using
+// sum_a c_a Xi_a = cs^2 F.  Pressure p* = sum f' + sum Xi / 2 with
+// sum_a Xi_a = cs^2 u . grad(rho).
+template <int D, typename T>
+__device__ __forceinline__ void velocity(Cell<T> &c)
+{
+    const T h = T(0.5) * c.irho;
+    c.ux = T(3) * c.Sx * c.irho + h * c.Fx;
+    c.uy = T(3) * c.Sy * c.irho + h * c.Fy;
+    c.uz = D == 3 ? T(3) * c.Sz * c.irho + h * c.Fz : T(0);
+    c.U = c.ux * c.drx + c.uy * c.dry + c.uz * c.drz;
+    c.pstar = c.S0 + T(0.5) * (T(1) / T(3)) * c.U;
+}
+
+template <int D, class P>
+__device__ __forceinline__ void eval_cell(const Geom &g, const Phys<typename P::T> &ph,
+                                          const Ptrs &p, int x, int y, int z,
+                                          Cell<typename P::T> &c)
+{
+    using T = typename P::T;
+    stencil<D, T>(g, static_cast<const T *>(p.phi), x, y, z, c);
+    closure<D, T>(ph, c);
+    flow_moments<D, P>(g, p, x, y, z, c);
+    velocity<D, T>(c);
+}
+
+// One 3-point sweep: central moments (k0, k1, k2) about u of a set on the
+// velocities {-1, 0, +1} -> the three values.
+template <typename T>
+__device__ __forceinline__ void sweep3(T k0, T k1, T k2, T u, T &vm, T &v0, T &vp)
+{
+    const T uu = u * u;
+    vm = T(0.5) * (k0 * (uu - u) + k1 * (T(2) * u - T(1)) + k2);
+    v0 = k0 * (T(1) - uu) - T(2) * u * k1 - k2;
+    vp = T(0.5) * (k0 * (uu + u) + k1 * (T(2) * u + T(1)) + k2);
+}
+
+// Post-collision unit-mass set from velocity and relaxed second-order central
+// moments: all cumulants above second order are zero, so the central moments
+// are Gaussian (Isserlis) products of the second-order ones.  Returned as the
+// deviation h*_a - w_a, computed without cancellation: the sweeps act on the
+// central-moment deviations from the rest state (second moments cs^2), and the
+// rest state's own image, prod_i (r + d(u_i)) - prod_i r with the D1Q3 weights
+// r = (1/6, 2/3, 1/6) and d(u) = ((u^2 - u)/2, -u^2, (u^2 + u)/2), is added in
+// expanded form.
+template <int D, typename T>
+__device__ __forceinline__ void rebuild(T ux, T uy, T uz, T Kxx, T Kyy, T Kzz, T Kxy, T Kxz, T Kyz,
+                                        T *hdev)
+{
+    constexpr T cs2 = T(1) / T(3);
+    const T r[3] = {T(1) / T(6), T(2) / T(3), T(1) / T(6)};
+    const T dx[3] = {T(0.5) * (ux * ux - ux), -ux * ux, T(0.5) * (ux * ux + ux)};
+    const T dy[3] = {T(0.5) * (uy * uy - uy), -uy * uy, T(0.5) * (uy * uy + uy)};
+    const T dxx = Kxx - cs2, dyy = Kyy - cs2;
+    if constexpr (D == 3) {
+        const T dz[3] = {T(0.5) * (uz * uz - uz), -uz * uz, T(0.5) * (uz * uz + uz)};
+        const T dzz = Kzz - cs2;
+        // m[a + 3b + 9c] = deviation of the central moment x^a y^b z^c
+        T m[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) m[i] = T(0);
+        m[2] = dxx;
+        m[6] = dyy;
+        m[18] = dzz;
+        m[4] = Kxy;
+        m[10] = Kxz;
+        m[12] = Kyz;
+        m[8] = dxx * Kyy + cs2 * dyy + T(2) * Kxy * Kxy;
+        m[20] = dxx * Kzz + cs2 * dzz + T(2) * Kxz * Kxz;
+        m[24] = dyy * Kzz + cs2 * dzz + T(2) * Kyz * Kyz;
+        m[14] = Kxx * Kyz + T(2) * Kxy * Kxz;
+        m[16] = Kyy * Kxz + T(2) * Kxy * Kyz;
+        m[22] = Kzz * Kxy + T(2) * Kxz * Kyz;
+        m[26] = dxx * Kyy * Kzz + cs2 * (dyy * Kzz + cs2 * dzz) +
+                T(2) * (Kxx * Kyz * Kyz + Kyy * Kxz * Kxz + Kzz * Kxy * Kxy) +
+                T(8) * Kxy * Kxz * Kyz;
+        // z digit: exponent -> velocity
+#pragma unroll
+        for (int i = 0; i < 9; ++i) sweep3(m[i], m[i + 9], m[i + 18], uz, m[i], m[i + 9], m[i + 18]);
+        // y digit
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int i = a + 9 * c;
+                sweep3(m[i], m[i + 3], m[i + 6], uy, m[i], m[i + 3], m[i + 6]);
+            }
+        // x digit
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const int i = 3 * j;
+            sweep3(m[i], m[i + 1], m[i + 2], ux, hdev[i], hdev[i + 1], hdev[i + 2]);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const T t1 = (r[j] + dy[j]) * (r[k] + dz[k]);
+                const T t2 = dy[j] * (r[k] + dz[k]) + r[j] * dz[k];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) hdev[i + 3 * j + 9 * k] += dx[i] * t1 + r[i] * t2;
+            }
+    } else {
+        T m[9];
+        m[0] = T(0);
+        m[1] = T(0);
+        m[2] = dxx;
+        m[3] = T(0);
+        m[4] = Kxy;
+        m[5] = T(0);
+        m[6] = dyy;
+        m[7] = T(0);
+        m[8] = dxx * Kyy + cs2 * dyy + T(2) * Kxy * Kxy;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sweep3(m[a], m[a + 3], m[a + 6], uy, m[a], m[a + 3], m[a + 6]);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int i = 3 * j;
+            sweep3(m[i], m[i + 1], m[i + 2], ux, hdev[i], hdev[i + 1], hdev[i + 2]);
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) hdev[i + 3 * j] += dx[i] * (r[j] + dy[j]) + r[i] * dy[j];
+        (void)uz; (void)Kzz; (void)Kxz; (void)Kyz;
+    }
+}
+
+// Source term of the flow populations (Sec. 2.3, dilatation term dropped):
+// Xi_a = cs^2 (Gamma_a - w_a)(c_a - u).grad(rho) + Gamma_a (c_a - u).F,
+// Gamma_a = f_eq_a / rho (second-order Hermite equilibrium, Appendix A).
+template <int D, typename T>
+__device__ __forceinline__ T source_xi(const Cell<T> &c, int a, T usq, T V, T &gam)
+{
+    const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
+    const T w = weight<D, T>(a);
+    const T cu = T(cx) * c.ux + T(cy) * c.uy + T(cz) * c.uz;
+    gam = w * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
+    const T cg = T(cx) * c.drx + T(cy) * c.dry + T(cz) * c.drz - c.U;
+    const T cf = T(cx) * c.Fx + T(cy) * c.Fy + T(cz) * c.Fz - V;
+    return (T(1) / T(3)) * (gam - w) * cg + gam * cf;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// phi(x) = sum_a g_a(x) over the pulled phase-field populations (Sec. 2.2).
+template <int D, class P>
+__device__ __forceinline__ void phi_cell(const Geom &g, const Ptrs &p, int x, int y, int z)
+{
+    using T = typename P::T;
+    constexpr int Q = Lat<D>::Q;
+    T s = 0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        int dir, cell;
+        pull_src<D>(g, x, y, z, a, &dir, &cell);
+        s += load_pop<D, typename P::G, T>(p.Gin, g.np, dir, cell, a, p.gp_in, nullptr);
+    }
+    static_cast<T *>(p.phi)[cell_of(g, x, y, z)] = s;
+}
+
+template <int D, class P>
+__global__ void __launch_bounds__(256) k_phi(Geom g, Ptrs p)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z * blockDim.z + threadIdx.z;
+    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+    phi_cell<D, P>(g, p, x, y, z);
+}
+
+// The fused update of one cell: stencil, closure, flow collision, phase-field
+// collision; post-collision values stored at the cell.
+template <int D, class P>
+__device__ __forceinline__ void collide_cell(const Geom &g, const Phys<typename P::T> &ph,
+                                             const Ptrs &p, int x, int y, int z)
+{
+    using T = typename P::T;
+    constexpr int Q = Lat<D>::Q;
+    constexpr T cs2 = T(1) / T(3);
+    const int me = cell_of(g, x, y, z);
+
+    Cell<T> c;
+    eval_cell<D, P>(g, ph, p, x, y, z, c);
+    const T usq = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
+    const T V = c.ux * c.Fx + c.uy * c.Fy + c.uz * c.Fz;
+    const T rcs2 = c.rho * cs2;
+
+    if (ph.collision == 0) {
+        // second moments of Xi in closed form (4th-order isotropy of the lattice)
+        auto xim = [&](T ui, T uj, T gi, T gj, T Fi, T Fj, bool diag) {
+            return cs2 * (cs2 * ((diag ? c.U : T(0)) + ui * gj + uj * gi) - ui * uj * c.U) +
+                   cs2 * (ui * Fj + uj * Fi) - ui * uj * V;
+        };
+        const T Mxx = c.Sxx + T(0.5) * xim(c.ux, c.ux, c.drx, c.drx, c.Fx, c.Fx, true);
+        const T Myy = c.Syy + T(0.5) * xim(c.uy, c.uy, c.dry, c.dry, c.Fy, c.Fy, true);
+        const T Mxy = c.Sxy + T(0.5) * xim(c.ux, c.uy, c.drx, c.dry, c.Fx, c.Fy, false);
+        // second-order central moments of the unit-mass set
+        const T pc = cs2 * c.pstar;
+        const T Pxx = T(3) * (Mxx - pc) * c.irho + cs2 - c.ux * c.ux;
+        const T Pyy = T(3) * (Myy - pc) * c.irho + cs2 - c.uy * c.uy;
+        const T Pxy = T(3) * Mxy * c.irho - c.ux * c.uy;
+        const T om1 = T(1) - c.omega;
+        T hd[Q];  // h* - w
+        if constexpr (D == 3) {
+            const T Mzz = c.Szz + T(0.5) * xim(c.uz, c.uz, c.drz, c.drz, c.Fz, c.Fz, true);
+            const T Mxz = c.Sxz + T(0.5) * xim(c.ux, c.uz, c.drx, c.drz, c.Fx, c.Fz, false);
+            const T Myz = c.Syz + T(0.5) * xim(c.uy, c.uz, c.dry, c.drz, c.Fy, c.Fz, false);
+            const T Pzz = T(3) * (Mzz - pc) * c.irho + cs2 - c.uz * c.uz;
+            const T Pxz = T(3) * Mxz * c.irho - c.ux * c.uz;
+            const T Pyz = T(3) * Myz * c.irho - c.uy * c.uz;
+            // deviatoric parts relax with omega, the trace goes to 3 cs^2
+            const T A = om1 * (Pxx - Pyy), B = om1 * (Pxx - Pzz);
+            const T Kxx = (T(1) + A + B) / T(3);
+            const T Kyy = (T(1) - T(2) * A + B) / T(3);
+            const T Kzz = (T(1) + A - T(2) * B) / T(3);
+            rebuild<D, T>(c.ux, c.uy, c.uz, Kxx, Kyy, Kzz, om1 * Pxy, om1 * Pxz, om1 * Pyz, hd);
+        } else {
+            const T A = om1 * (Pxx - Pyy);
+            rebuild<D, T>(c.ux, c.uy, T(0), cs2 + T(0.5) * A, cs2 - T(0.5) * A, T(0), om1 * Pxy,
+                          T(0), T(0), hd);
+        }
+        // f'* = rho cs^2 (h* - w) + w p* + Xi/2
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            T gam;
+            const T xi = source_xi<D, T>(c, a, usq, V, gam);
+            const T dev = rcs2 * hd[a] + T(0.5) * xi;
+            store_dev<D, typename P::F, T>(p.Fout, g.np, a, me, dev, c.pstar, rcs2);
+        }
+    } else {
+        // single relaxation time: f'* = f' - omega (f' - f'_eq) + (1 - omega/2) Xi
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
+            int dir, cell;
+            pull_src<D>(g, x, y, z, a, &dir, &cell);
+            const T v = load_pop<D, typename P::F, T>(p.Fin, g.np, dir, cell, a, p.fp_in, p.fr_in);
+            const T w = weight<D, T>(a);
+            const T cu = T(cx) * c.ux + T(cy) * c.uy + T(cz) * c.uz;
+            T gam;
+            const T xi = source_xi<D, T>(c, a, usq, V, gam);
+            const T feq_dev = w * rcs2 * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
+            const T vdev = v - w * c.pstar;
+            const T dev = vdev - c.omega * (vdev - feq_dev) + (T(1) - T(0.5) * c.omega) * xi;
+            store_dev<D, typename P::F, T>(p.Fout, g.np, a, me, dev, c.pstar, rcs2);
+        }
+    }
+    if constexpr (P::F::shifted) {
+        p.fp_out[me] = float(c.pstar);
+        p.fr_out[me] = float(rcs2);
+    }
+
+    // conservative Allen-Cahn: g* = g + (g_eq - g)/taubar + S_bar (Sec. 2.2)
+    const T nrm = sqrt(c.gx * c.gx + c.gy * c.gy + c.gz * c.gz + T(1e-24));
+    const T nx = c.gx / nrm, ny = c.gy / nrm, nz = c.gz / nrm;
+    const T src = ph.src_pre * ph.four_W * c.phi * (T(1) - c.phi);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
+        int dir, cell;
+        pull_src<D>(g, x, y, z, a, &dir, &cell);
+        const T v = load_pop<D, typename P::G, T>(p.Gin, g.np, dir, cell, a, p.gp_in, nullptr);
+        const T w = weight<D, T>(a);
+        const T cu = T(cx) * c.ux + T(cy) * c.uy + T(cz) * c.uz;
+        const T geq = w * c.phi * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
+        const T cn = T(cx) * nx + T(cy) * ny + T(cz) * nz;
+        const T gout = v + (geq - v) * ph.inv_tpb + w * cn * src;
+        if constexpr (P::G::shifted)
+            store_dev<D, typename P::G, T>(p.Gout, g.np, a, me, gout - w * c.phi, c.phi, T(1));
+        else
+            static_cast<typename P::G::raw *>(p.Gout)[(long long)a * g.np + me] =
+                typename P::G::raw(gout);
+    }
+    if constexpr (P::G::shifted) p.gp_out[me] = float(c.phi);
+}
+
+template <int D, class P>
+__global__ void __launch_bounds__(256) k_collide(Geom g, Phys<typename P::T> ph, Ptrs p)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z * blockDim.z + threadIdx.z;
+    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+    collide_cell<D, P>(g, ph, p, x, y, z);
+}
+
+// Equilibrium initial state, computed in FP64 for every storage format and
+// scattered to the slots the first step pulls from.
+template <int D, class P>
+__global__ void __launch_bounds__(256) k_init(Geom g, PhysD ph, Ptrs p, const double *dphi,
+                                              const double *du, const double *dp)
+{
+    constexpr int Q = Lat<D>::Q;
+    constexpr double cs2 = 1.0 / 3.0;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z * blockDim.z + threadIdx.z;
+    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+    const int me = cell_of(g, x, y, z);
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    Cell<double> c;
+    stencil<D, double>(g, dphi, x, y, z, c);
+    closure<D, double>(to_phys<double>(ph), c);
+    const double ux = du[me], uy = du[N + me], uz = D == 3 ? du[2 * N + me] : 0.0;
+    const double h = 0.5 * c.irho;
+    // population velocity and pressure such that the scheme reports u and p
+    const double vx = ux - h * c.Fx, vy = uy - h * c.Fy, vz = uz - h * c.Fz;
+    const double U = ux * c.drx + uy * c.dry + uz * c.drz;
+    const double ppop = dp[me] - 0.5 * cs2 * U;
+    const double usq = ux * ux + uy * uy + uz * uz, vsq = vx * vx + vy * vy + vz * vz;
+    const double rcs2 = c.rho * cs2;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
+        const double w = weight<D, double>(a);
+        const double cv = cx * vx + cy * vy + cz * vz;
+        const double cu = cx * ux + cy * uy + cz * uz;
+        const double fdev = w * rcs2 * (3.0 * cv + 4.5 * cv * cv - 1.5 * vsq);
+        const double gval = w * c.phi * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        int dir, cell;
+        pull_src<D>(g, x, y, z, a, &dir, &cell);
+        // the slot's own cell supplies the shift/scale of shifted formats
+        if constexpr (P::F::shifted) {
+            const float w32 = weight<D, float>(a);
+            const double f = w * ppop + fdev;
+            static_cast<__half *>(p.Fout)[(long long)dir * g.np + cell] =
+                __float2half(float((f - w * p.fp_out[cell]) / (w32 * p.fr_out[cell])));
+        } else {
+            static_cast<typename P::F::raw *>(p.Fout)[(long long)dir * g.np + cell] =
+                typename P::F::raw(w * ppop + fdev);
+        }
+        if constexpr (P::G::shifted) {
+            const float w32 = weight<D, float>(a);
+            static_cast<__half *>(p.Gout)[(long long)dir * g.np + cell] =
+                __float2half(float((gval - w * p.gp_out[cell]) / w32));
+        } else {
+            static_cast<typename P::G::raw *>(p.Gout)[(long long)dir * g.np + cell] =
+                typename P::G::raw(gval);
+        }
+    }
+}
+
+// Shift/scale of shifted formats from FP64 phi and pressure fields.
+template <int D>
+__global__ void __launch_bounds__(256) k_set_refs(Geom g, PhysD ph, Ptrs p, const double *dphi,
+                                                  const double *dp)
+{
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (p.fp_out) {
+        p.fp_out[i] = float(dp[i]);
+        p.fr_out[i] = float((ph.rho_l + ph.drho * dphi[i]) / 3.0);
+    }
+    if (p.gp_out) p.gp_out[i] = float(dphi[i]);
+}
+
+template <int D, class P>
+__global__ void __launch_bounds__(256) k_get_pop(Geom g, Ptrs p, int which, int a0, int a1,
+                                                 double *dst)
+{
+    using T = typename P::T;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z * blockDim.z + threadIdx.z;
+    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+    const int me = cell_of(g, x, y, z);
+    const long long N = (long long)g.nx * g.ny * g.nz;
+#pragma unroll
+    for (int a = 0; a < Lat<D>::Q; ++a) {
+        if (a < a0 || a >= a1) continue;
+        int dir, cell;
+        pull_src<D>(g, x, y, z, a, &dir, &cell);
+        const T v = which == 0
+                        ? load_pop<D, typename P::F, T>(p.Fin, g.np, dir, cell, a, p.fp_in, p.fr_in)
+                        : load_pop<D, typename P::G, T>(p.Gin, g.np, dir, cell, a, p.gp_in, nullptr);
+        dst[(long long)(a - a0) * N + me] = double(v);
+    }
+}
+
+template <int D, class P>
+__global__ void __launch_bounds__(256) k_set_pop(Geom g, Ptrs p, int which, int a0, int a1,
+                                                 const double *src)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z * blockDim.z + threadIdx.z;
+    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+    const int me = cell_of(g, x, y, z);
+    const long long N = (long long)g.nx * g.ny * g.nz;
+#pragma unroll
+    for (int a = 0; a < Lat<D>::Q; ++a) {
+        if (a < a0 || a >= a1) continue;
+        int dir, cell;
+        pull_src<D>(g, x, y, z, a, &dir, &cell);
+        const double v = src[(long long)(a - a0) * N + me];
+        const double w = weight<D, double>(a);
+        const float w32 = weight<D, float>(a);
+        if (which == 0) {
+            if constexpr (P::F::shifted)
+                static_cast<__half *>(p.Fout)[(long long)dir * g.np + cell] =
+                    __float2half(float((v - w * p.fp_out[cell]) / (w32 * p.fr_out[cell])));
+            else
+                static_cast<typename P::F::raw *>(p.Fout)[(long long)dir * g.np + cell] =
+                    typename P::F::raw(v);
+        } else {
+            if constexpr (P::G::shifted)
+                static_cast<__half *>(p.Gout)[(long long)dir * g.np + cell] =
+                    __float2half(float((v - w * p.gp_out[cell]) / w32));
+            else
+                static_cast<typename P::G::raw *>(p.Gout)[(long long)dir * g.np + cell] =
+                    typename P::G::raw(v);
+        }
+    }
+}
+
+template <int D, class P>
+__global__ void __launch_bounds__(256) k_field(Geom g, Phys<typename P::T> ph, Ptrs p, int field,
+                                               double *dst)
+{
+    using T = typename P::T;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z * blockDim.z + threadIdx.z;
+    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+    Cell<T> c;
+    eval_cell<D, P>(g, ph, p, x, y, z, c);
+    T v = field == 0 ? c.phi : field == 1 ? c.rho : field == 2 ? c.ux : field == 3 ? c.uy
+        : field == 4 ? c.uz : c.pstar;
+    dst[cell_of(g, x, y, z)] = double(v);
+}
+
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+// Per-block partial sums in a fixed order: grid-stride over cells, wavefront
+// shuffles, then the four wavefronts of the block in order.
+template <int D, class P>
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(Geom g, Phys<typename P::T> ph,
+                                                               Ptrs p, double *partials)
+{
+    using T = typename P::T;
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (long long i = (long long)blockIdx.x * RED_THREADS + threadIdx.x; i < N;
+         i += (long long)gridDim.x * RED_THREADS) {
+        const int x = int(i % g.nx), y = int((i / g.nx) % g.ny), z = int(i / ((long long)g.nx * g.ny));
+        Cell<T> c;
+        eval_cell<D, P>(g, ph, p, x, y, z, c);
+        const double rho = double(c.rho);
+        const double ux = double(c.ux), uy = double(c.uy), uz = double(c.uz);
+        const double um = sqrt(ux * ux + uy * uy + uz * uz);
+        const double ph0 = double(c.phi);
+        acc[0] += ph0;
+        acc[1] += rho * ux;
+        acc[2] += rho * uy;
+        acc[3] += rho * uz;
+        acc[4] = fmax(acc[4], um);
+        if (!isfinite(ph0) || !isfinite(rho * ux) || !isfinite(rho * uy) || !isfinite(rho * uz) ||
+            !isfinite(um))
+            acc[5] += 1.0;
+    }
+    __shared__ double red[RED_THREADS / 64][6];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double v = k == 4 ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) red[wv][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        double v = red[0][k];
+        for (int w = 1; w < RED_THREADS / 64; ++w) v = k == 4 ? fmax(v, red[w][k]) : v + red[w][k];
+        partials[blockIdx.x * 8 + k] = v;
+    }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double *partials, int nblocks,
+                                                             double *out)
+{
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += RED_THREADS)
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            acc[k] = k == 4 ? fmax(acc[k], partials[b * 8 + k]) : acc[k] + partials[b * 8 + k];
+    __shared__ double red[RED_THREADS / 64][6];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double v = k == 4 ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) red[wv][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        double v = red[0][k];
+        for (int w = 1; w < RED_THREADS / 64; ++w) v = k == 4 ? fmax(v, red[w][k]) : v + red[w][k];
+        out[k] = v;
+    }
+}
+
+// ------------------------------------------------------------------ batches
+// Many independent domains advance in the same two launches.  Persistent
+// blocks stride over a tile list; each tile names its domain, whose geometry,
+// parameters, buffers and active step window are read from the domain table.
+// The per-cell arithmetic is the single-domain path's (phi_cell,
+// collide_cell), so a domain's result does not depend on the batch it is in.
+
+__device__ __forceinline__ Ptrs batch_ptrs(const BatchDom &d, int in)
+{
+    Ptrs p;
+    p.Fin = d.F[in];
+    p.Gin = d.G[in];
+    p.Fout = d.F[1 - in];
+    p.Gout = d.G[1 - in];
+    p.phi = d.phi;
+    p.fp_in = d.fp[in];
+    p.fr_in = d.fr[in];
+    p.gp_in = d.gp[in];
+    p.fp_out = d.fp[1 - in];
+    p.fr_out = d.fr[1 - in];
+    p.gp_out = d.gp[1 - in];
+    return p;
+}
+
+template <int D, class P, bool PHI>
+__global__ void __launch_bounds__(256) kb_step(const BatchDom *__restrict__ doms,
+                                               const BatchTile *__restrict__ tiles,
+                                               const int *ntiles, const long long *tbase,
+                                               int step_off)
+{
+    using T = typename P::T;
+    const long long t = *tbase + step_off;
+    const int nt = *ntiles;
+    for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
+        const BatchTile tl = tiles[ti];
+        const BatchDom &d = doms[tl.dom];
+        if (t < d.first || t >= d.last) continue;
+        const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y, z = tl.z0 + threadIdx.z;
+        if (x >= d.g.nx || y >= d.g.ny || z >= d.g.nz) continue;
+        const Ptrs p = batch_ptrs(d, int((t - d.first) & 1));
+        if constexpr (PHI)
+            phi_cell<D, P>(d.g, p, x, y, z);
+        else
+            collide_cell<D, P>(d.g, to_phys<T>(d.ph), p, x, y, z);
+    }
+}
+
+__global__ void k_set_i64(long long *ptr, long long v) { *ptr = v; }
+
+// --------------------------------------------------------------- launchers
+
+static dim3 grid_for(const Ctx &c)
+{
+    return dim3((c.g.nx + c.block.x - 1) / c.block.x, (c.g.ny + c.block.y - 1) / c.block.y,
+                (c.g.nz + c.block.z - 1) / c.block.z);
+}
+
+// Calls fn.template operator()<D, P>() for the context's dimension and storage.
+template <class Fn>
+static hipError_t dispatch(const Ctx &c, Fn &&fn)
+{
+    if (c.dim == 2) {
+        switch (c.storage) {
+        case ST_FP64: return fn.template operator()<2, P64>();
+        case ST_FP32: return fn.template operator()<2, P32>();
+        case ST_FP16S: return fn.template operator()<2, P16>();
+        case ST_FP16S_ALL: return fn.template operator()<2, P16A>();
+        }
+    } else if (c.dim == 3) {
+        switch (c.storage) {
+        case ST_FP64: return fn.template operator()<3, P64>();
+        case ST_FP32: return fn.template operator()<3, P32>();
+        case ST_FP16S: return fn.template operator()<3, P16>();
+        case ST_FP16S_ALL: return fn.template operator()<3, P16A>();
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_phi(const Ctx &c)
+{
+    return dispatch(c, [&]<int D, class P>() {
+        hipLaunchKernelGGL((k_phi<D, P>), grid_for(c), c.block, 0, c.stream, c.g, c.p);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_collide(const Ctx &c)
+{
+    return dispatch(c, [&]<int D, class P>() {
+        hipLaunchKernelGGL((k_collide<D, P>), grid_for(c), c.block, 0, c.stream, c.g,
+                           to_phys<typename P::T>(c.ph), c.p);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_init(const Ctx &c, const double *phi, const double *u, const double *pr)
+{
+    return dispatch(c, [&]<int D, class P>() {
+        hipLaunchKernelGGL((k_init<D, P>), grid_for(c), c.block, 0, c.stream, c.g, c.ph, c.p, phi,
+                           u, pr);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_set_refs(const Ctx &c, const double *phi, const double *pr)
+{
+    const long long N = (long long)c.g.nx * c.g.ny * c.g.nz;
+    const dim3 grid((unsigned)((N + 255) / 256));
+    if (c.dim == 2)
+        hipLaunchKernelGGL(k_set_refs<2>, grid, dim3(256), 0, c.stream, c.g, c.ph, c.p, phi, pr);
+    else
+        hipLaunchKernelGGL(k_set_refs<3>, grid, dim3(256), 0, c.stream, c.g, c.ph, c.p, phi, pr);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_pop(const Ctx &c, int which, int a0, int a1, double *dst)
+{
+    return dispatch(c, [&]<int D, class P>() {
+        hipLaunchKernelGGL((k_get_pop<D, P>), grid_for(c), c.block, 0, c.stream, c.g, c.p, which,
+                           a0, a1, dst);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_set_pop(const Ctx &c, int which, int a0, int a1, const double *src)
+{
+    return dispatch(c, [&]<int D, class P>() {
+        hipLaunchKernelGGL((k_set_pop<D, P>), grid_for(c), c.block, 0, c.stream, c.g, c.p, which,
+                           a0, a1, src);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_field(const Ctx &c, int field, double *dst)
+{
+    return dispatch(c, [&]<int D, class P>() {
+        hipLaunchKernelGGL((k_field<D, P>), grid_for(c), c.block, 0, c.stream, c.g,
+                           to_phys<typename P::T>(c.ph), c.p, field, dst);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_batch_step(int dim, int storage, const BatchDom *doms, const BatchTile *tiles,
+                             const int *ntiles, const long long *tbase, int step_off, dim3 block,
+                             int grid, hipStream_t stream)
+{
+    Ctx c{};
+    c.dim = dim;
+    c.storage = storage;
+    return dispatch(c, [&]<int D, class P>() {
+        hipLaunchKernelGGL((kb_step<D, P, true>), dim3(grid), block, 0, stream, doms, tiles, ntiles,
+                           tbase, step_off);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((kb_step<D, P, false>), dim3(grid), block, 0, stream, doms, tiles,
+                           ntiles, tbase, step_off);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_set_i64(long long *ptr, long long v, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, stream, ptr, v);
+    return hipGetLastError();
+}
+
+int reduce_blocks(const Ctx &c)
+{
+    const long long N = (long long)c.g.nx * c.g.ny * c.g.nz;
+    const long long need = (N + RED_THREADS - 1) / RED_THREADS;
+    return int(need < RED_BLOCKS ? need : RED_BLOCKS);
+}
+
+hipError_t launch_reduce(const Ctx &c, double *partials, double *out)
+{
+    const int nb = reduce_blocks(c);
+    hipError_t e = dispatch(c, [&]<int D, class P>() {
+        hipLaunchKernelGGL((k_reduce_partial<D, P>), dim3(nb), dim3(RED_THREADS), 0, c.stream, c.g,
+                           to_phys<typename P::T>(c.ph), c.p, partials);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, c.stream, partials, nb, out);
+    return hipGetLastError();
+}
+
+}  // namespace mplb

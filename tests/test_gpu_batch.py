@@ -1,0 +1,124 @@
+"""GPU tests of the batched path: many independent domains of uneven size and
+parameters advanced together (persistent launches over a tile list, graph
+replay).  A domain's result must be bitwise identical alone and in the mix
+(same per-cell arithmetic), for any activity window, and match the oracle on
+the first steps."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2101_06769_amd import inputs
+from tests.helpers import from_abi, gpu_available, rel_err
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    from paper_2101_06769_amd import mplb
+
+
+def small_batch_cases(count=5, seed=3):
+    return inputs.batch_rti3d(count=count, seed=seed, edges=(8, 12, 16), steps=40)
+
+
+def solver_for(case, storage="fp32"):
+    s = mplb.Solver(case.params, storage=storage)
+    s.init(case.phi, case.u, case.p)
+    return s
+
+
+def state(s):
+    return s.get_populations(0), s.get_populations(1)
+
+
+@pytest.mark.parametrize("chunk", [0, 8])
+def test_batch_equals_alone_bitwise(chunk):
+    cases = small_batch_cases()
+    steps = 24
+    alone = []
+    for c in cases:
+        s = solver_for(c)
+        s.step(steps)
+        alone.append(state(s))
+    b = mplb.Batch(3, "fp32", capacity=8, max_tiles=1 << 14)
+    b.set_graph_chunk(chunk)
+    solvers = [solver_for(c) for c in cases]
+    for s in solvers:
+        b.attach(s, steps)
+    b.step(steps + 5)  # extra steps: every window has closed
+    for s, (fa, ga) in zip(solvers, alone):
+        fb, gb = state(s)
+        assert s.steps_done() == steps
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
+def test_staggered_windows_and_reuse_of_slots():
+    cases = small_batch_cases(count=4, seed=7)
+    plan = [(0, 4), (2, 7), (5, 6), (12, 4)]  # (attach at batch step, steps)
+    alone = []
+    for c, (_, n) in zip(cases, plan):
+        s = solver_for(c)
+        s.step(n)
+        alone.append(state(s))
+    b = mplb.Batch(3, "fp32", capacity=2, max_tiles=1 << 14)  # 2 slots: forces reuse
+    b.set_graph_chunk(4)
+    solvers = [solver_for(c) for c in cases]
+    slots = {}
+    done = set()
+    for t in range(20):
+        for i, (t0, n) in enumerate(plan):
+            if t == t0:
+                # free finished slots first
+                for j, sl in list(slots.items()):
+                    if b.remaining(sl) == 0:
+                        b.detach(sl)
+                        del slots[j]
+                        done.add(j)
+                slots[i] = b.attach(solvers[i], n)
+        b.step(1)
+    for i, s in enumerate(solvers):
+        assert s.steps_done() == plan[i][1], (i, s.steps_done())
+        fb, gb = state(s)
+        assert np.array_equal(alone[i][0], fb) and np.array_equal(alone[i][1], gb), i
+
+
+def test_batch_matches_oracle_on_first_steps():
+    cases = small_batch_cases(count=3, seed=11)
+    b = mplb.Batch(3, "fp32", capacity=4, max_tiles=1 << 14)
+    solvers = [solver_for(c) for c in cases]
+    for s in solvers:
+        b.attach(s, 2)
+    b.step(2)
+    for c, s in zip(cases, solvers):
+        po = oracle.params_from_dict(c.params)
+        f, g = oracle.step(po, *oracle.init(po, c.phi, c.u, c.p), 2)
+        assert rel_err(from_abi(3, s.get_populations(0)), f) < 2e-6
+        assert rel_err(from_abi(3, s.get_populations(1)), g) < 2e-6
+
+
+def test_autotuner_picks_a_valid_shape_and_result_is_shape_independent():
+    case = inputs.rti3d_multimode(24, 0.5, 500.0, seed=2)
+    s = solver_for(case)
+    best, ms = s.tune_block(steps=4)
+    assert best[0] * best[1] * best[2] <= 256 and ms > 0
+    ref = solver_for(case)
+    ref.step(6)
+    for shape in [(64, 4, 1), (32, 2, 2), best]:
+        t = solver_for(case)
+        t.set_block(*shape)
+        t.step(6)
+        fa, ga = state(ref)
+        fb, gb = state(t)
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), shape
+
+
+def test_attached_solver_cannot_step_alone():
+    case = small_batch_cases(count=1)[0]
+    b = mplb.Batch(3, "fp32", capacity=1, max_tiles=1 << 12)
+    s = solver_for(case)
+    slot = b.attach(s, 3)
+    with pytest.raises(mplb.MplbError):
+        s.step(1)
+    with pytest.raises(mplb.MplbError):
+        b.attach(s, 3)
+    b.detach(slot)
+    s.step(1)
