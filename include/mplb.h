@@ -205,7 +205,8 @@ typedef struct mplb_batch mplb_batch;
 size_t mplb_batch_table_bytes(int32_t capacity, int64_t max_tiles);
 
 /* dev_table: 256-byte aligned device memory of mplb_batch_table_bytes();
- * hip_stream must be the stream of every solver that will be attached. */
+ * hip_stream: a created (non-NULL) stream, which must also be the stream of
+ * every solver that will be attached (step chunks are captured from it). */
 int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t max_tiles,
                       void *dev_table, size_t table_bytes, void *hip_stream, mplb_batch **out);
 

@@ -496,7 +496,7 @@ int mplb_set_populations(mplb_solver *s, int32_t which, const double *host_in)
 /* ------------------------------------------------------------------ batches */
 
 struct mplb_batch {
-    int dim, storage, capacity;
+    int dim, storage, collision, capacity;
     long long max_tiles;
     hipStream_t stream;
     mplb::BatchDom *d_doms;
@@ -591,6 +591,8 @@ int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t ma
         return fail(MPLB_EINVAL, "capacity and max_tiles must be >= 1");
     if (!dev_table || reinterpret_cast<uintptr_t>(dev_table) % ALIGN)
         return fail(MPLB_EINVAL, "table memory must be non-NULL and 256-byte aligned");
+    if (!hip_stream)
+        return fail(MPLB_EINVAL, "a batch needs its own stream (graphs cannot capture the null stream)");
     size_t od, ot, on, ob;
     const size_t need = table_layout(capacity, max_tiles, &od, &ot, &on, &ob);
     if (table_bytes < need) return fail(MPLB_ENOMEM, "batch table memory too small");
@@ -599,6 +601,7 @@ int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t ma
     char *base = static_cast<char *>(dev_table);
     b->dim = dim;
     b->storage = storage;
+    b->collision = MPLB_COLL_CUMULANT;
     b->capacity = capacity;
     b->max_tiles = max_tiles;
     b->stream = static_cast<hipStream_t>(hip_stream);
@@ -649,6 +652,14 @@ int mplb_batch_attach(mplb_batch *b, mplb_solver *s, int64_t nsteps, int32_t *sl
     if (nsteps < 0) return fail(MPLB_EINVAL, "nsteps must be >= 0");
     if (s->prm.dim != b->dim || s->prm.storage != b->storage)
         return fail(MPLB_EINVAL, "solver dimension/storage differ from the batch's");
+    bool empty = true;
+    for (auto *o : b->slot) empty = empty && !o;
+    if (empty) {
+        if (b->collision != s->prm.collision) drop_graph(b);
+        b->collision = s->prm.collision;
+    } else if (s->prm.collision != b->collision) {
+        return fail(MPLB_EINVAL, "solvers of one batch must share the collision operator");
+    }
     if (s->stream != b->stream) return fail(MPLB_EINVAL, "solver and batch streams differ");
     if (!s->ready) return fail(MPLB_ESTATE, "solver is not initialised");
     if (s->attached) return fail(MPLB_ESTATE, "solver is already attached");
@@ -721,17 +732,20 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
         HIPCHK(mplb::launch_set_i64(b->d_tbase, b->t, b->stream));
         if (b->chunk > 0 && left >= b->chunk) {
             if (!b->have_graph) {
-                hipGraph_t graph;
+                hipGraph_t graph = nullptr;
                 HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
                 hipError_t e = hipSuccess;
                 for (int k = 0; k < b->chunk && e == hipSuccess; ++k)
-                    e = mplb::launch_batch_step(b->dim, b->storage, b->d_doms, b->d_tiles,
+                    e = mplb::launch_batch_step(b->dim, b->storage, b->collision, b->d_doms, b->d_tiles,
                                                 b->d_ntiles, b->d_tbase, k, b->block, b->grid,
                                                 b->stream);
-                hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
-                if (e != hipSuccess || e2 != hipSuccess)
+                // always end the capture, so that a failure leaves the stream usable
+                const hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+                if (e != hipSuccess || e2 != hipSuccess) {
+                    if (graph) (void)hipGraphDestroy(graph);
                     return fail(MPLB_EDEVICE, std::string("graph capture: ") +
                                                   hipGetErrorString(e != hipSuccess ? e : e2));
+                }
                 e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
                 if (e != hipSuccess)
@@ -742,7 +756,7 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
             b->t += b->chunk;
             done += b->chunk;
         } else {
-            HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->d_doms, b->d_tiles, b->d_ntiles,
+            HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->collision, b->d_doms, b->d_tiles, b->d_ntiles,
                                            b->d_tbase, 0, b->block, b->grid, b->stream));
             b->t += 1;
             done += 1;

@@ -87,9 +87,9 @@ struct BatchTile {
 
 // One step of every active domain: persistent blocks stride over the tile
 // list (*ntiles entries); the batch step index is *tbase + step_off.
-hipError_t launch_batch_step(int dim, int storage, const BatchDom *doms, const BatchTile *tiles,
-                             const int *ntiles, const long long *tbase, int step_off, dim3 block,
-                             int grid, hipStream_t stream);
+hipError_t launch_batch_step(int dim, int storage, int collision, const BatchDom *doms,
+                             const BatchTile *tiles, const int *ntiles, const long long *tbase,
+                             int step_off, dim3 block, int grid, hipStream_t stream);
 hipError_t launch_set_i64(long long *ptr, long long v, hipStream_t stream);
 
 }  // namespace mplb

@@ -131,11 +131,12 @@ struct Cell {
 // w (phi(x+c) + phi(x-c) - 2 phi(x)), so that uniform and mirror-symmetric
 // fields give exactly zero gradient components.
 template <int D, typename T>
-__device__ __forceinline__ void stencil(const Geom &g, const T *__restrict__ phi, int x, int y,
-                                        int z, Cell<T> &c)
+__device__ __forceinline__ void stencil(const Loc &l, const T *__restrict__ phi, Cell<T> &c)
 {
     constexpr int Q = Lat<D>::Q;
-    const T p0 = phi[cell_of(g, x, y, z)];
+    const Geom &g = *l.g;
+    const int x = l.x, y = l.y, z = l.z;
+    const T p0 = phi[l.me];
     T gx = 0, gy = 0, gz = 0, lap = 0;
 #pragma unroll
     for (int a = Q / 2 + 1; a < Q; ++a) {
@@ -180,27 +181,36 @@ __device__ __forceinline__ void closure(const Phys<T> &ph, Cell<T> &c)
     c.omega = T(1) / (T(3) * nu + T(0.5));
 }
 
-// Raw moments of the pulled flow populations (orders 0..2).
+// Raw moments of the pulled flow populations (orders 0..2), accumulated over
+// pairs of opposite directions (f_a + f_opp for even moments, f_a - f_opp for
+// odd ones) so that the pressure part w p cancels exactly in the odd moments
+// and the velocity part cancels before it reaches the even ones.
 template <int D, class P>
-__device__ __forceinline__ void flow_moments(const Geom &g, const Ptrs &p, int x, int y, int z,
+__device__ __forceinline__ void flow_moments(const Loc &nb, long long np, const Ptrs &p,
                                              Cell<typename P::T> &c)
 {
     using T = typename P::T;
     constexpr int Q = Lat<D>::Q;
-    T S0 = 0, Sx = 0, Sy = 0, Sz = 0, Sxx = 0, Syy = 0, Szz = 0, Sxy = 0, Sxz = 0, Syz = 0;
+    int dir, cell;
+    pull_src<D>(*nb.g, nb.x, nb.y, nb.z, Q / 2, &dir, &cell);
+    T S0 = load_pop<D, typename P::F, T>(p.Fin, np, dir, cell, Q / 2, p.fp_in, p.fr_in);
+    T Sx = 0, Sy = 0, Sz = 0, Sxx = 0, Syy = 0, Szz = 0, Sxy = 0, Sxz = 0, Syz = 0;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
+    for (int a = Q / 2 + 1; a < Q; ++a) {
+        const int b = opposite<D>(a);
         const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
-        int dir, cell;
-        pull_src<D>(g, x, y, z, a, &dir, &cell);
-        const T v = load_pop<D, typename P::F, T>(p.Fin, g.np, dir, cell, a, p.fp_in, p.fr_in);
-        S0 += v;
-        if (cx) { Sx += T(cx) * v; Sxx += v; }
-        if (cy) { Sy += T(cy) * v; Syy += v; }
-        if (cz) { Sz += T(cz) * v; Szz += v; }
-        if (cx && cy) Sxy += T(cx * cy) * v;
-        if (cx && cz) Sxz += T(cx * cz) * v;
-        if (cy && cz) Syz += T(cy * cz) * v;
+        pull_src<D>(*nb.g, nb.x, nb.y, nb.z, a, &dir, &cell);
+        const T va = load_pop<D, typename P::F, T>(p.Fin, np, dir, cell, a, p.fp_in, p.fr_in);
+        pull_src<D>(*nb.g, nb.x, nb.y, nb.z, b, &dir, &cell);
+        const T vb = load_pop<D, typename P::F, T>(p.Fin, np, dir, cell, b, p.fp_in, p.fr_in);
+        const T sp = va + vb, dm = va - vb;
+        S0 += sp;
+        if (cx) { Sx += T(cx) * dm; Sxx += sp; }
+        if (cy) { Sy += T(cy) * dm; Syy += sp; }
+        if (cz) { Sz += T(cz) * dm; Szz += sp; }
+        if (cx && cy) Sxy += T(cx * cy) * sp;
+        if (cx && cz) Sxz += T(cx * cz) * sp;
+        if (cy && cz) Syz += T(cy * cz) * sp;
     }
     c.S0 = S0; c.Sx = Sx; c.Sy = Sy; c.Sz = Sz;
     c.Sxx = Sxx; c.Syy = Syy; c.Szz = Szz; c.Sxy = Sxy; c.Sxz = Sxz; c.Syz = Syz;
@@ -221,14 +231,14 @@ __device__ __forceinline__ void velocity(Cell<T> &c)
 }
 
 template <int D, class P>
-__device__ __forceinline__ void eval_cell(const Geom &g, const Phys<typename P::T> &ph,
-                                          const Ptrs &p, int x, int y, int z,
+__device__ __forceinline__ void eval_cell(const Loc &nb, long long np,
+                                          const Phys<typename P::T> &ph, const Ptrs &p,
                                           Cell<typename P::T> &c)
 {
     using T = typename P::T;
-    stencil<D, T>(g, static_cast<const T *>(p.phi), x, y, z, c);
+    stencil<D, T>(nb, static_cast<const T *>(p.phi), c);
     closure<D, T>(ph, c);
-    flow_moments<D, P>(g, p, x, y, z, c);
+    flow_moments<D, P>(nb, np, p, c);
     velocity<D, T>(c);
 }
 
@@ -244,25 +254,26 @@ __device__ __forceinline__ void sweep3(T k0, T k1, T k2, T u, T &vm, T &v0, T &v
 }
 
 // Post-collision unit-mass set from velocity and relaxed second-order central
-// moments: all cumulants above second order are zero, so the central moments
-// are Gaussian (Isserlis) products of the second-order ones.  Returned as the
+// moments (diagonal ones given as deviations dxx = Kxx - cs^2, ...): all
+// cumulants above second order are zero, so the central moments are Gaussian
+// (Isserlis) products of the second-order ones.  Returned as the
 // deviation h*_a - w_a, computed without cancellation: the sweeps act on the
 // central-moment deviations from the rest state (second moments cs^2), and the
 // rest state's own image, prod_i (r + d(u_i)) - prod_i r with the D1Q3 weights
 // r = (1/6, 2/3, 1/6) and d(u) = ((u^2 - u)/2, -u^2, (u^2 + u)/2), is added in
 // expanded form.
 template <int D, typename T>
-__device__ __forceinline__ void rebuild(T ux, T uy, T uz, T Kxx, T Kyy, T Kzz, T Kxy, T Kxz, T Kyz,
+__device__ __forceinline__ void rebuild(T ux, T uy, T uz, T dxx, T dyy, T dzz, T Kxy, T Kxz, T Kyz,
                                         T *hdev)
 {
     constexpr T cs2 = T(1) / T(3);
     const T r[3] = {T(1) / T(6), T(2) / T(3), T(1) / T(6)};
     const T dx[3] = {T(0.5) * (ux * ux - ux), -ux * ux, T(0.5) * (ux * ux + ux)};
     const T dy[3] = {T(0.5) * (uy * uy - uy), -uy * uy, T(0.5) * (uy * uy + uy)};
-    const T dxx = Kxx - cs2, dyy = Kyy - cs2;
+    const T Kxx = cs2 + dxx, Kyy = cs2 + dyy;
     if constexpr (D == 3) {
         const T dz[3] = {T(0.5) * (uz * uz - uz), -uz * uz, T(0.5) * (uz * uz + uz)};
-        const T dzz = Kzz - cs2;
+        const T Kzz = cs2 + dzz;
         // m[a + 3b + 9c] = deviation of the central moment x^a y^b z^c
         T m[27];
 #pragma unroll
@@ -330,7 +341,7 @@ __device__ __forceinline__ void rebuild(T ux, T uy, T uz, T Kxx, T Kyy, T Kzz, T
         for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int i = 0; i < 3; ++i) hdev[i + 3 * j] += dx[i] * (r[j] + dy[j]) + r[i] * dy[j];
-        (void)uz; (void)Kzz; (void)Kxz; (void)Kyz;
+        (void)uz; (void)dzz; (void)Kxz; (void)Kyz; (void)Kxx;
     }
 }
 
@@ -353,7 +364,7 @@ __device__ __forceinline__ T source_xi(const Cell<T> &c, int a, T usq, T V, T &g
 
 // phi(x) = sum_a g_a(x) over the pulled phase-field populations (Sec. 2.2).
 template <int D, class P>
-__device__ __forceinline__ void phi_cell(const Geom &g, const Ptrs &p, int x, int y, int z)
+__device__ __forceinline__ void phi_body(const Loc &nb, long long np, const Ptrs &p)
 {
     using T = typename P::T;
     constexpr int Q = Lat<D>::Q;
@@ -361,10 +372,17 @@ __device__ __forceinline__ void phi_cell(const Geom &g, const Ptrs &p, int x, in
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
         int dir, cell;
-        pull_src<D>(g, x, y, z, a, &dir, &cell);
-        s += load_pop<D, typename P::G, T>(p.Gin, g.np, dir, cell, a, p.gp_in, nullptr);
+        pull_src<D>(*nb.g, nb.x, nb.y, nb.z, a, &dir, &cell);
+        s += load_pop<D, typename P::G, T>(p.Gin, np, dir, cell, a, p.gp_in, nullptr);
     }
-    static_cast<T *>(p.phi)[cell_of(g, x, y, z)] = s;
+    static_cast<T *>(p.phi)[nb.me] = s;
+}
+
+template <int D, class P>
+__device__ __forceinline__ void phi_cell(const Geom &g, const Ptrs &p, int x, int y, int z)
+{
+    const Loc nb{&g, x, y, z, cell_of(g, x, y, z)};
+    phi_body<D, P>(nb, g.np, p);
 }
 
 template <int D, class P>
@@ -379,22 +397,25 @@ __global__ void __launch_bounds__(256) k_phi(Geom g, Ptrs p)
 
 // The fused update of one cell: stencil, closure, flow collision, phase-field
 // collision; post-collision values stored at the cell.
-template <int D, class P>
-__device__ __forceinline__ void collide_cell(const Geom &g, const Phys<typename P::T> &ph,
-                                             const Ptrs &p, int x, int y, int z)
+template <int D, class P, int COLL>
+__device__ __forceinline__ void collide_body(const Loc &nb, const Geom &g,
+                                             const Phys<typename P::T> &ph, const Ptrs &p)
 {
     using T = typename P::T;
     constexpr int Q = Lat<D>::Q;
     constexpr T cs2 = T(1) / T(3);
-    const int me = cell_of(g, x, y, z);
+    const int me = nb.me;
 
     Cell<T> c;
-    eval_cell<D, P>(g, ph, p, x, y, z, c);
+    eval_cell<D, P>(nb, g.np, ph, p, c);
     const T usq = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
     const T V = c.ux * c.Fx + c.uy * c.Fy + c.uz * c.Fz;
     const T rcs2 = c.rho * cs2;
 
-    if (ph.collision == 0) {
+
+
+
+    if constexpr (COLL == 0) {
         // second moments of Xi in closed form (4th-order isotropy of the lattice)
         auto xim = [&](T ui, T uj, T gi, T gj, T Fi, T Fj, bool diag) {
             return cs2 * (cs2 * ((diag ? c.U : T(0)) + ui * gj + uj * gi) - ui * uj * c.U) +
@@ -403,10 +424,12 @@ __device__ __forceinline__ void collide_cell(const Geom &g, const Phys<typename 
         const T Mxx = c.Sxx + T(0.5) * xim(c.ux, c.ux, c.drx, c.drx, c.Fx, c.Fx, true);
         const T Myy = c.Syy + T(0.5) * xim(c.uy, c.uy, c.dry, c.dry, c.Fy, c.Fy, true);
         const T Mxy = c.Sxy + T(0.5) * xim(c.ux, c.uy, c.drx, c.dry, c.Fx, c.Fy, false);
-        // second-order central moments of the unit-mass set
+        // second-order central moments of the unit-mass set, diagonal ones as
+        // deviations from cs^2 (they are cs^2 + O(u^2) and relax by a small
+        // amount, so carrying cs^2 along would cost digits in FP32)
         const T pc = cs2 * c.pstar;
-        const T Pxx = T(3) * (Mxx - pc) * c.irho + cs2 - c.ux * c.ux;
-        const T Pyy = T(3) * (Myy - pc) * c.irho + cs2 - c.uy * c.uy;
+        const T Pxx = T(3) * (Mxx - pc) * c.irho - c.ux * c.ux;
+        const T Pyy = T(3) * (Myy - pc) * c.irho - c.uy * c.uy;
         const T Pxy = T(3) * Mxy * c.irho - c.ux * c.uy;
         const T om1 = T(1) - c.omega;
         T hd[Q];  // h* - w
@@ -414,35 +437,47 @@ __device__ __forceinline__ void collide_cell(const Geom &g, const Phys<typename 
             const T Mzz = c.Szz + T(0.5) * xim(c.uz, c.uz, c.drz, c.drz, c.Fz, c.Fz, true);
             const T Mxz = c.Sxz + T(0.5) * xim(c.ux, c.uz, c.drx, c.drz, c.Fx, c.Fz, false);
             const T Myz = c.Syz + T(0.5) * xim(c.uy, c.uz, c.dry, c.drz, c.Fy, c.Fz, false);
-            const T Pzz = T(3) * (Mzz - pc) * c.irho + cs2 - c.uz * c.uz;
+            const T Pzz = T(3) * (Mzz - pc) * c.irho - c.uz * c.uz;
             const T Pxz = T(3) * Mxz * c.irho - c.ux * c.uz;
             const T Pyz = T(3) * Myz * c.irho - c.uy * c.uz;
             // deviatoric parts relax with omega, the trace goes to 3 cs^2
             const T A = om1 * (Pxx - Pyy), B = om1 * (Pxx - Pzz);
-            const T Kxx = (T(1) + A + B) / T(3);
-            const T Kyy = (T(1) - T(2) * A + B) / T(3);
-            const T Kzz = (T(1) + A - T(2) * B) / T(3);
-            rebuild<D, T>(c.ux, c.uy, c.uz, Kxx, Kyy, Kzz, om1 * Pxy, om1 * Pxz, om1 * Pyz, hd);
+            rebuild<D, T>(c.ux, c.uy, c.uz, (A + B) / T(3), (B - T(2) * A) / T(3),
+                          (A - T(2) * B) / T(3), om1 * Pxy, om1 * Pxz, om1 * Pyz, hd);
         } else {
             const T A = om1 * (Pxx - Pyy);
-            rebuild<D, T>(c.ux, c.uy, T(0), cs2 + T(0.5) * A, cs2 - T(0.5) * A, T(0), om1 * Pxy,
-                          T(0), T(0), hd);
+            rebuild<D, T>(c.ux, c.uy, T(0), T(0.5) * A, T(-0.5) * A, T(0), om1 * Pxy, T(0), T(0),
+                          hd);
         }
-        // f'* = rho cs^2 (h* - w) + w p* + Xi/2
+        // f'* = rho cs^2 (h* - w) + w p* + Xi/2.  Plain formats take the rest
+        // direction as the remainder of sum f'* = sum f' + sum Xi, so the
+        // zeroth moment does not drift with the rounding of the weights.
+        T fsum = 0;
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
+            if (a == Q / 2 && !P::F::shifted) continue;
             T gam;
             const T xi = source_xi<D, T>(c, a, usq, V, gam);
             const T dev = rcs2 * hd[a] + T(0.5) * xi;
-            store_dev<D, typename P::F, T>(p.Fout, g.np, a, me, dev, c.pstar, rcs2);
+            if constexpr (P::F::shifted) {
+                store_dev<D, typename P::F, T>(p.Fout, g.np, a, me, dev, c.pstar, rcs2);
+            } else {
+                const T v = dev + weight<D, T>(a) * c.pstar;
+                fsum += v;
+                static_cast<typename P::F::raw *>(p.Fout)[(long long)a * g.np + me] =
+                    typename P::F::raw(v);
+            }
         }
+        if constexpr (!P::F::shifted)
+            static_cast<typename P::F::raw *>(p.Fout)[(long long)(Q / 2) * g.np + me] =
+                typename P::F::raw((c.S0 + cs2 * c.U) - fsum);
     } else {
         // single relaxation time: f'* = f' - omega (f' - f'_eq) + (1 - omega/2) Xi
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
             const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
             int dir, cell;
-            pull_src<D>(g, x, y, z, a, &dir, &cell);
+            pull_src<D>(*nb.g, nb.x, nb.y, nb.z, a, &dir, &cell);
             const T v = load_pop<D, typename P::F, T>(p.Fin, g.np, dir, cell, a, p.fp_in, p.fr_in);
             const T w = weight<D, T>(a);
             const T cu = T(cx) * c.ux + T(cy) * c.uy + T(cz) * c.uz;
@@ -459,38 +494,56 @@ __device__ __forceinline__ void collide_cell(const Geom &g, const Phys<typename 
         p.fr_out[me] = float(rcs2);
     }
 
-    // conservative Allen-Cahn: g* = g + (g_eq - g)/taubar + S_bar (Sec. 2.2)
+    // conservative Allen-Cahn: g* = g + (g_eq - g)/taubar + S_bar (Sec. 2.2).
+    // Plain formats take the rest direction as the remainder of sum g* = phi.
     const T nrm = sqrt(c.gx * c.gx + c.gy * c.gy + c.gz * c.gz + T(1e-24));
     const T nx = c.gx / nrm, ny = c.gy / nrm, nz = c.gz / nrm;
     const T src = ph.src_pre * ph.four_W * c.phi * (T(1) - c.phi);
+    T gsum = 0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
+        if (a == Q / 2 && !P::G::shifted) continue;
         const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
         int dir, cell;
-        pull_src<D>(g, x, y, z, a, &dir, &cell);
+        pull_src<D>(*nb.g, nb.x, nb.y, nb.z, a, &dir, &cell);
         const T v = load_pop<D, typename P::G, T>(p.Gin, g.np, dir, cell, a, p.gp_in, nullptr);
         const T w = weight<D, T>(a);
         const T cu = T(cx) * c.ux + T(cy) * c.uy + T(cz) * c.uz;
         const T geq = w * c.phi * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
         const T cn = T(cx) * nx + T(cy) * ny + T(cz) * nz;
         const T gout = v + (geq - v) * ph.inv_tpb + w * cn * src;
-        if constexpr (P::G::shifted)
+        if constexpr (P::G::shifted) {
             store_dev<D, typename P::G, T>(p.Gout, g.np, a, me, gout - w * c.phi, c.phi, T(1));
-        else
+        } else {
+            gsum += gout;
             static_cast<typename P::G::raw *>(p.Gout)[(long long)a * g.np + me] =
                 typename P::G::raw(gout);
+        }
     }
+    if constexpr (!P::G::shifted)
+        static_cast<typename P::G::raw *>(p.Gout)[(long long)(Q / 2) * g.np + me] =
+            typename P::G::raw(c.phi - gsum);
     if constexpr (P::G::shifted) p.gp_out[me] = float(c.phi);
+
+
 }
 
-template <int D, class P>
+template <int D, class P, int COLL>
+__device__ __forceinline__ void collide_cell(const Geom &g, const Phys<typename P::T> &ph,
+                                             const Ptrs &p, int x, int y, int z)
+{
+    const Loc nb{&g, x, y, z, cell_of(g, x, y, z)};
+    collide_body<D, P, COLL>(nb, g, ph, p);
+}
+
+template <int D, class P, int COLL>
 __global__ void __launch_bounds__(256) k_collide(Geom g, Phys<typename P::T> ph, Ptrs p)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z * blockDim.z + threadIdx.z;
     if (x >= g.nx || y >= g.ny || z >= g.nz) return;
-    collide_cell<D, P>(g, ph, p, x, y, z);
+    collide_cell<D, P, COLL>(g, ph, p, x, y, z);
 }
 
 // Equilibrium initial state, computed in FP64 for every storage format and
@@ -508,7 +561,7 @@ __global__ void __launch_bounds__(256) k_init(Geom g, PhysD ph, Ptrs p, const do
     const int me = cell_of(g, x, y, z);
     const long long N = (long long)g.nx * g.ny * g.nz;
     Cell<double> c;
-    stencil<D, double>(g, dphi, x, y, z, c);
+    stencil<D, double>(Loc{&g, x, y, z, cell_of(g, x, y, z)}, dphi, c);
     closure<D, double>(to_phys<double>(ph), c);
     const double ux = du[me], uy = du[N + me], uz = D == 3 ? du[2 * N + me] : 0.0;
     const double h = 0.5 * c.irho;
@@ -633,7 +686,8 @@ __global__ void __launch_bounds__(256) k_field(Geom g, Phys<typename P::T> ph, P
     const int z = blockIdx.z * blockDim.z + threadIdx.z;
     if (x >= g.nx || y >= g.ny || z >= g.nz) return;
     Cell<T> c;
-    eval_cell<D, P>(g, ph, p, x, y, z, c);
+    const Loc nb{&g, x, y, z, cell_of(g, x, y, z)};
+    eval_cell<D, P>(nb, g.np, ph, p, c);
     T v = field == 0 ? c.phi : field == 1 ? c.rho : field == 2 ? c.ux : field == 3 ? c.uy
         : field == 4 ? c.uz : c.pstar;
     dst[cell_of(g, x, y, z)] = double(v);
@@ -668,7 +722,8 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(Geom g, Phys<typ
          i += (long long)gridDim.x * RED_THREADS) {
         const int x = int(i % g.nx), y = int((i / g.nx) % g.ny), z = int(i / ((long long)g.nx * g.ny));
         Cell<T> c;
-        eval_cell<D, P>(g, ph, p, x, y, z, c);
+        const Loc nb{&g, x, y, z, cell_of(g, x, y, z)};
+        eval_cell<D, P>(nb, g.np, ph, p, c);
         const double rho = double(c.rho);
         const double ux = double(c.ux), uy = double(c.uy), uz = double(c.uz);
         const double um = sqrt(ux * ux + uy * uy + uz * uz);
@@ -746,7 +801,7 @@ __device__ __forceinline__ Ptrs batch_ptrs(const BatchDom &d, int in)
     return p;
 }
 
-template <int D, class P, bool PHI>
+template <int D, class P, int COLL, bool PHI>
 __global__ void __launch_bounds__(256) kb_step(const BatchDom *__restrict__ doms,
                                                const BatchTile *__restrict__ tiles,
                                                const int *ntiles, const long long *tbase,
@@ -765,7 +820,7 @@ __global__ void __launch_bounds__(256) kb_step(const BatchDom *__restrict__ doms
         if constexpr (PHI)
             phi_cell<D, P>(d.g, p, x, y, z);
         else
-            collide_cell<D, P>(d.g, to_phys<T>(d.ph), p, x, y, z);
+            collide_cell<D, P, COLL>(d.g, to_phys<T>(d.ph), p, x, y, z);
     }
 }
 
@@ -812,8 +867,12 @@ hipError_t launch_phi(const Ctx &c)
 hipError_t launch_collide(const Ctx &c)
 {
     return dispatch(c, [&]<int D, class P>() {
-        hipLaunchKernelGGL((k_collide<D, P>), grid_for(c), c.block, 0, c.stream, c.g,
-                           to_phys<typename P::T>(c.ph), c.p);
+        if (c.ph.collision == 0)
+            hipLaunchKernelGGL((k_collide<D, P, 0>), grid_for(c), c.block, 0, c.stream, c.g,
+                               to_phys<typename P::T>(c.ph), c.p);
+        else
+            hipLaunchKernelGGL((k_collide<D, P, 1>), grid_for(c), c.block, 0, c.stream, c.g,
+                               to_phys<typename P::T>(c.ph), c.p);
         return hipGetLastError();
     });
 }
@@ -865,20 +924,24 @@ hipError_t launch_field(const Ctx &c, int field, double *dst)
     });
 }
 
-hipError_t launch_batch_step(int dim, int storage, const BatchDom *doms, const BatchTile *tiles,
-                             const int *ntiles, const long long *tbase, int step_off, dim3 block,
-                             int grid, hipStream_t stream)
+hipError_t launch_batch_step(int dim, int storage, int collision, const BatchDom *doms,
+                             const BatchTile *tiles, const int *ntiles, const long long *tbase,
+                             int step_off, dim3 block, int grid, hipStream_t stream)
 {
     Ctx c{};
     c.dim = dim;
     c.storage = storage;
     return dispatch(c, [&]<int D, class P>() {
-        hipLaunchKernelGGL((kb_step<D, P, true>), dim3(grid), block, 0, stream, doms, tiles, ntiles,
-                           tbase, step_off);
+        hipLaunchKernelGGL((kb_step<D, P, 0, true>), dim3(grid), block, 0, stream, doms, tiles,
+                           ntiles, tbase, step_off);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((kb_step<D, P, false>), dim3(grid), block, 0, stream, doms, tiles,
-                           ntiles, tbase, step_off);
+        if (collision == 0)
+            hipLaunchKernelGGL((kb_step<D, P, 0, false>), dim3(grid), block, 0, stream, doms,
+                               tiles, ntiles, tbase, step_off);
+        else
+            hipLaunchKernelGGL((kb_step<D, P, 1, false>), dim3(grid), block, 0, stream, doms,
+                               tiles, ntiles, tbase, step_off);
         return hipGetLastError();
     });
 }

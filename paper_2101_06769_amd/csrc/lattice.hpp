@@ -93,4 +93,10 @@ __device__ __forceinline__ void pull_src(const Geom &g, int x, int y, int z, int
     }
 }
 
+// The cell a thread works on.
+struct Loc {
+    const Geom *g;
+    int x, y, z, me;
+};
+
 }  // namespace mplb

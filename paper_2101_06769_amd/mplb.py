@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmplb.so")
+LIB_PATH = os.environ.get("MPLB_LIBRARY", os.path.join(HERE, "libmplb.so"))
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ESTATE = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_WALL, BC_SYMMETRY = 0, 1, 2
@@ -286,7 +286,9 @@ class Batch:
         self.table = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         base = self.table.data_ptr()
         off = (-base) % 256
-        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        # a dedicated stream at the default priority: graphs cannot capture the
+        # null stream; attached solvers must be created on this stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(dev)
         h = ctypes.c_void_p()
         st = STORAGE[storage] if isinstance(storage, str) else int(storage)
         check(lib.mplb_batch_create(int(dim), st, int(capacity), int(max_tiles),

@@ -20,8 +20,8 @@ def small_batch_cases(count=5, seed=3):
     return inputs.batch_rti3d(count=count, seed=seed, edges=(8, 12, 16), steps=40)
 
 
-def solver_for(case, storage="fp32"):
-    s = mplb.Solver(case.params, storage=storage)
+def solver_for(case, storage="fp32", stream=None):
+    s = mplb.Solver(case.params, storage=storage, stream=stream)
     s.init(case.phi, case.u, case.p)
     return s
 
@@ -41,7 +41,7 @@ def test_batch_equals_alone_bitwise(chunk):
         alone.append(state(s))
     b = mplb.Batch(3, "fp32", capacity=8, max_tiles=1 << 14)
     b.set_graph_chunk(chunk)
-    solvers = [solver_for(c) for c in cases]
+    solvers = [solver_for(c, stream=b.stream) for c in cases]
     for s in solvers:
         b.attach(s, steps)
     b.step(steps + 5)  # extra steps: every window has closed
@@ -61,7 +61,7 @@ def test_staggered_windows_and_reuse_of_slots():
         alone.append(state(s))
     b = mplb.Batch(3, "fp32", capacity=2, max_tiles=1 << 14)  # 2 slots: forces reuse
     b.set_graph_chunk(4)
-    solvers = [solver_for(c) for c in cases]
+    solvers = [solver_for(c, stream=b.stream) for c in cases]
     slots = {}
     done = set()
     for t in range(20):
@@ -84,7 +84,7 @@ def test_staggered_windows_and_reuse_of_slots():
 def test_batch_matches_oracle_on_first_steps():
     cases = small_batch_cases(count=3, seed=11)
     b = mplb.Batch(3, "fp32", capacity=4, max_tiles=1 << 14)
-    solvers = [solver_for(c) for c in cases]
+    solvers = [solver_for(c, stream=b.stream) for c in cases]
     for s in solvers:
         b.attach(s, 2)
     b.step(2)
@@ -114,7 +114,7 @@ def test_autotuner_picks_a_valid_shape_and_result_is_shape_independent():
 def test_attached_solver_cannot_step_alone():
     case = small_batch_cases(count=1)[0]
     b = mplb.Batch(3, "fp32", capacity=1, max_tiles=1 << 12)
-    s = solver_for(case)
+    s = solver_for(case, stream=b.stream)
     slot = b.attach(s, 3)
     with pytest.raises(mplb.MplbError):
         s.step(1)

@@ -13,8 +13,8 @@ order parameter's gradient vanishes the interface normal is set by round-off
 differences of any two implementations grow to the size of the bulk phi
 deviations; the multi-step tests therefore check that GPU-vs-oracle
 differences stay within a small multiple of the oracle-vs-oracle difference
-under a perturbation of the GPU's precision, and check the invariants
-(phase mass, symmetry) exactly.
+when the oracle's populations are perturbed by one rounding of the GPU's
+precision after every step, and check the invariants (phase mass) directly.
 """
 import numpy as np
 import pytest
@@ -169,17 +169,21 @@ def test_c1_rayleigh_taylor_fp64_early_steps_match_oracle():
 
 
 def sensitivity_floor(po, f, g, steps, amp, seed=0):
-    """Oracle-vs-oracle field differences after `steps` when the initial
-    populations carry a relative perturbation of size amp."""
+    """Oracle-vs-oracle field differences after `steps` when the populations
+    carry a relative perturbation of size amp after every step (one rounding
+    of the GPU's storage precision per step)."""
     rng = np.random.default_rng(seed)
     fa, ga = oracle.step(po, f, g, steps)
-    fb, gb = oracle.step(po, f * (1 + amp * rng.uniform(-1, 1, f.shape)),
-                         g * (1 + amp * rng.uniform(-1, 1, g.shape)), steps)
+    fb, gb = f, g
+    for _ in range(steps):
+        fb, gb = oracle.step(po, fb, gb, 1)
+        fb = fb * (1 + amp * rng.uniform(-1, 1, fb.shape))
+        gb = gb * (1 + amp * rng.uniform(-1, 1, gb.shape))
     A, B = oracle.fields(po, fa, ga), oracle.fields(po, fb, gb)
     return A, {k: np.abs(A[k] - B[k]).max() for k in ("phi", "u", "p")}
 
 
-@pytest.mark.parametrize("storage,amp", [("fp64", 1e-15), ("fp32", 6e-8)])
+@pytest.mark.parametrize("storage,amp", [("fp64", 2.0 ** -53), ("fp32", 2.0 ** -24)])
 def test_c1_rayleigh_taylor_2000_steps_within_roundoff_floor(storage, amp):
     case = inputs.rti2d()
     po = oracle.params_from_dict(case.params)
