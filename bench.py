@@ -63,6 +63,9 @@ def main():
     ap.add_argument("--nz", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="instead of the benchmark, time a plain device-to-device copy of this "
+                         "many MiB (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -74,6 +77,22 @@ def main():
     from paper_2101_06769_amd import inputs, mplb
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_probe_bytes": n, "ms": ms, "GBs_read_plus_write": 2 * n / ms / 1e6}))
+        return
     case = inputs.rti3d(nz=args.nz)
     N = case.ncells
     s = mplb.Solver(case.params, storage=args.storage)

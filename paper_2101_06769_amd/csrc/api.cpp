@@ -123,6 +123,9 @@ Layout make_layout(const mplb_params *p)
     return L;
 }
 
+// Default block: as wide in x as the lattice (up to 256 cells) so that the
+// cache lines split by the x-shifted pulls stay inside one workgroup, then
+// filled along y and z to 256 threads.
 dim3 default_block(const mplb_params *p)
 {
     auto pow2 = [](int v, int cap) {
@@ -130,7 +133,7 @@ dim3 default_block(const mplb_params *p)
         while (b < v && b < cap) b <<= 1;
         return b;
     };
-    const int bx = pow2(p->n[0], 64);
+    const int bx = pow2(p->n[0], 256);
     const int by = pow2(p->n[1], 256 / bx);
     const int bz = pow2(p->n[2], 256 / (bx * by));
     return dim3(bx, by, bz);

@@ -362,6 +362,16 @@ __device__ __forceinline__ T source_xi(const Cell<T> &c, int a, T usq, T V, T &g
 
 // ------------------------------------------------------------------ kernels
 
+// Occupancy target of the fused collision: five wavefronts per SIMD for the
+// FP32-arithmetic D3Q27 kernels (at most 96 VGPRs; measured faster than four
+// without the cap), the compiler's choice otherwise.
+template <int D, class P, int COLL>
+constexpr int collide_waves()
+{
+    return (D == 3 && sizeof(typename P::T) == 4) ? 5 : 1;
+}
+
+
 // phi(x) = sum_a g_a(x) over the pulled phase-field populations (Sec. 2.2).
 template <int D, class P>
 __device__ __forceinline__ void phi_body(const Loc &nb, long long np, const Ptrs &p)
@@ -464,13 +474,13 @@ __device__ __forceinline__ void collide_body(const Loc &nb, const Geom &g,
             } else {
                 const T v = dev + weight<D, T>(a) * c.pstar;
                 fsum += v;
-                static_cast<typename P::F::raw *>(p.Fout)[(long long)a * g.np + me] =
-                    typename P::F::raw(v);
+                __builtin_nontemporal_store(typename P::F::raw(v),
+                    &static_cast<typename P::F::raw *>(p.Fout)[(long long)a * g.np + me]);
             }
         }
         if constexpr (!P::F::shifted)
-            static_cast<typename P::F::raw *>(p.Fout)[(long long)(Q / 2) * g.np + me] =
-                typename P::F::raw((c.S0 + cs2 * c.U) - fsum);
+            __builtin_nontemporal_store(typename P::F::raw((c.S0 + cs2 * c.U) - fsum),
+            &static_cast<typename P::F::raw *>(p.Fout)[(long long)(Q / 2) * g.np + me]);
     } else {
         // single relaxation time: f'* = f' - omega (f' - f'_eq) + (1 - omega/2) Xi
 #pragma unroll
@@ -516,13 +526,13 @@ __device__ __forceinline__ void collide_body(const Loc &nb, const Geom &g,
             store_dev<D, typename P::G, T>(p.Gout, g.np, a, me, gout - w * c.phi, c.phi, T(1));
         } else {
             gsum += gout;
-            static_cast<typename P::G::raw *>(p.Gout)[(long long)a * g.np + me] =
-                typename P::G::raw(gout);
+            __builtin_nontemporal_store(typename P::G::raw(gout),
+                &static_cast<typename P::G::raw *>(p.Gout)[(long long)a * g.np + me]);
         }
     }
     if constexpr (!P::G::shifted)
-        static_cast<typename P::G::raw *>(p.Gout)[(long long)(Q / 2) * g.np + me] =
-            typename P::G::raw(c.phi - gsum);
+        __builtin_nontemporal_store(typename P::G::raw(c.phi - gsum),
+            &static_cast<typename P::G::raw *>(p.Gout)[(long long)(Q / 2) * g.np + me]);
     if constexpr (P::G::shifted) p.gp_out[me] = float(c.phi);
 
 
@@ -537,7 +547,8 @@ __device__ __forceinline__ void collide_cell(const Geom &g, const Phys<typename 
 }
 
 template <int D, class P, int COLL>
-__global__ void __launch_bounds__(256) k_collide(Geom g, Phys<typename P::T> ph, Ptrs p)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(collide_waves<D, P, COLL>())))
+k_collide(Geom g, Phys<typename P::T> ph, Ptrs p)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -802,7 +813,8 @@ __device__ __forceinline__ Ptrs batch_ptrs(const BatchDom &d, int in)
 }
 
 template <int D, class P, int COLL, bool PHI>
-__global__ void __launch_bounds__(256) kb_step(const BatchDom *__restrict__ doms,
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(PHI ? 1 : collide_waves<D, P, COLL>()))) kb_step(const BatchDom *__restrict__ doms,
                                                const BatchTile *__restrict__ tiles,
                                                const int *ntiles, const long long *tbase,
                                                int step_off)
