@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -27,10 +29,40 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 #   phi:     read 27 g, write phi                          -> 4 * (27 + 1)     = 112
 ALG_BYTES = {("fp32", 3): {"collide": 436, "phi": 112, "method": 440},
              ("fp64", 3): {"collide": 872, "phi": 224, "method": 880},
-             ("fp16s", 3): {"collide": 2 * 27 * 2 + 2 * 27 * 4 + 4 + 8 * 2, "phi": 27 * 4 + 4,
-                            "method": 340},
+             # FP16-shifted flow set: 27 x 2 B each way, plus the per-cell shift
+             # and scale (2 x 4 B) read at the source cells and written back
+             ("fp16s", 3): {"collide": 2 * 27 * 2 + 2 * 27 * 4 + 4 + 2 * 8, "phi": 27 * 4 + 4,
+                            "method": 2 * 27 * 2 + 2 * 27 * 4 + 8 + 2 * 8},
+             # both sets FP16-shifted; the phase-field shift (phi, 4 B) too
+             ("fp16s_all", 3): {"collide": 4 * 27 * 2 + 4 + 2 * 8 + 2 * 4, "phi": 27 * 2 + 4 + 4,
+                                "method": 4 * 27 * 2 + 8 + 2 * 8 + 2 * 4},
              ("fp32", 2): {"collide": 4 * (2 * 2 * 9 + 1), "phi": 4 * (9 + 1), "method": 152},
              ("fp64", 2): {"collide": 8 * (2 * 2 * 9 + 1), "phi": 8 * (9 + 1), "method": 304}}
+
+
+KERNEL_SOURCES = ("kernels.hip", "lattice.hpp", "internal.h")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_collide_k_phi_rti3d_128x128x512_fp32_hbm_bytes.md")
+
+
+def profiled_traffic(storage, nz):
+    """HBM bytes per k_collide launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (each counter scaled by its reading for a plain copy of
+    known size).  None unless that summary was taken on this workload and on
+    kernel sources identical to the ones in the tree."""
+    import hashlib
+
+    if storage != "fp32" or nz != 512 or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2101_06769_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    text = open(TRAFFIC_PROFILE).read()
+    blob = text.split("```json", 1)[1].split("```", 1)[0]
+    rec = json.loads(blob)
+    if rec["sources_sha256"] != h.hexdigest():
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(case_fn, min_seconds=10.0):
@@ -54,15 +86,199 @@ def cpu_baseline(case_fn, min_seconds=10.0):
                       "case, FP64, %.1f s" % (steps, case.ncells, el)}
 
 
+def bench_batch(args):
+    """64 independent 3-D Rayleigh-Taylor domains of uneven size (seed 0:
+    edge in {32, 48, 64, 96, 128}, z = 4 edge, Atwood in [0.1, 0.9], Re in
+    [100, 3000], random-phase multimode interface), FP32, `steps` steps each.
+    Plain: one domain at a time, each with its own launches, on one stream.
+    Batched: all domains in the same persistent launches, block shape from the
+    autotuner, chunks of steps replayed as a HIP graph.  States are resident
+    before either timed region starts; both start from the same initial state."""
+    import torch
+
+    from paper_2101_06769_amd import inputs, mplb
+
+    steps = args.batch_steps
+    cases = inputs.batch_rti3d(count=args.domains, seed=0, steps=steps)
+    cells = sum(c.ncells for c in cases)
+    b = mplb.Batch(3, "fp32", capacity=len(cases), max_tiles=1 << 22)
+    b.set_graph_chunk(16)
+    solvers = [mplb.Solver(c.params, storage="fp32", stream=b.stream) for c in cases]
+
+    def reset():
+        for c, sv in zip(cases, solvers):
+            sv.init(c.phi, c.u, c.p)
+
+    # autotune the batch block on the workload itself, then start over
+    reset()
+    slots = [b.attach(sv, 10 ** 9) for sv in solvers]
+    best, _ = b.tune_block(steps=3)
+    for sl in slots:
+        b.detach(sl)
+    # plain: one domain per launch pair, sequentially
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sv in solvers:
+        sv.step(steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain_phi = [sv.read(0) for sv in solvers[:4]]
+    # batched: one untimed chunk captures the step graph, then start over
+    reset()
+    slots = [b.attach(sv, steps) for sv in solvers]
+    b.step(16)
+    for sl in slots:
+        b.detach(sl)
+    reset()
+    for sv in solvers:
+        b.attach(sv, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = all(np.array_equal(a, sv.read(0)) for a, sv in zip(plain_phi, solvers[:4]))
+    line = {
+        "metric": "batched jobs/s (64 uneven 3-D Rayleigh-Taylor domains)",
+        "value": round(len(cases) / t_batch, 3),
+        "unit": "jobs/s",
+        "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(t_batch / steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "64 independent 3-D Rayleigh-Taylor domains, edge in "
+                               "{32,48,64,96,128}, z = 4 edge, At U[0.1,0.9], Re U[100,3000], "
+                               "FP32, %d steps each" % steps,
+                   "cells": cells, "parallelism": "single GPU"},
+        "batched": {"jobs_per_s": round(len(cases) / t_batch, 3), "makespan_s": round(t_batch, 3),
+                    "mlups": round(cells * steps / t_batch / 1e6, 1), "block": list(best)},
+        "plain": {"jobs_per_s": round(len(cases) / t_plain, 3), "makespan_s": round(t_plain, 3),
+                  "mlups": round(cells * steps / t_plain / 1e6, 1)},
+        "speedup_vs_plain": round(t_plain / t_batch, 3),
+        "batched_equals_plain_bitwise": bool(same),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_splash(args):
+    """3-D droplet impact on a thin liquid sheet, 512 x 512 x 256 (density
+    ratio 1000, viscosity ratio 15, We 8000, Re 1000, D = 64, sheet 0.1 D,
+    U0 0.05): the same `splash_steps` steps in FP64, FP32 and FP16-shifted
+    storage.  Reports each format's MLUPS and its field errors against the
+    FP64 run (the FP64 GPU path is the one held to the oracle at 1e-12)."""
+    import torch
+
+    from paper_2101_06769_amd import inputs, mplb
+
+    case = inputs.splash3d()
+    U0 = case.meta["U0"]
+    N = case.ncells
+    out = {}
+    ref = None
+    for storage in ("fp64", "fp32", "fp16s", "fp16s_all"):
+        s = mplb.Solver(case.params, storage=storage)
+        s.init(case.phi, case.u, case.p)
+        s.step(5)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.step(args.splash_steps)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        f = s.fields()
+        red, rc = s.reduce()
+        rec = {"mlups": round(N * args.splash_steps / (ms / 1e3) / 1e6, 1),
+               "ms_per_step": round(ms / args.splash_steps, 4),
+               "alg_GBs": round(ALG_BYTES[(storage, 3)]["method"] * N * args.splash_steps /
+                                (ms / 1e3) / 1e9, 1),
+               "status": "ok" if rc == mplb.OK else "unstable",
+               "phase_mass_rel_drift": abs(red[0] - case.phi.sum()) / case.phi.sum()}
+        if ref is None:
+            ref = f
+        else:
+            rec["max_abs_dphi"] = float(np.abs(f["phi"] - ref["phi"]).max())
+            rec["max_abs_du_over_U0"] = float(np.abs(f["u"] - ref["u"]).max() / U0)
+            rec["max_abs_dp_over_rhoU0sq"] = float(np.abs(f["p"] - ref["p"]).max() / (U0 * U0))
+        out[storage] = rec
+        del s, f
+        torch.cuda.empty_cache()
+    line = {
+        "metric": "MLUPS (flow+phase field) at fixed error vs FP64: droplet splash, FP32 vs FP16",
+        "value": out["fp16s"]["mlups"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.splash_steps, "warmup": 5,
+        "ms_per_step": out["fp16s"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f16s+f32", "data": "synthetic",
+        "config": {"workload": "3-D droplet impact on a thin liquid sheet, 512x512x256, density "
+                               "ratio 1000, viscosity ratio 15, We 8000, Re 1000, D 64, U0 0.05",
+                   "cells": N, "parallelism": "single GPU"},
+        "by_storage": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """Serving: seeded Poisson arrivals (20/s) of 2-D solves (Rayleigh-Taylor,
+    static drop, impacting drop; edge log-uniform 64..1024, density ratio
+    3..1000, steps 500..20000), FP32, replayed in real time through the
+    continuous-batching server and through the one-at-a-time baseline."""
+    import torch
+
+    from paper_2101_06769_amd import inputs, mplb, serve
+
+    specs = inputs.serving_spec(seed=1, count=args.requests, rate=args.rate)
+    # warm-up: kernel loading and graph instantiation outside the replay
+    warm = inputs.serving_spec(seed=99, count=2, rate=1000.0, edge_range=(64, 64),
+                               steps_range=(40, 40))
+    serve.serve_batched(warm, realtime=False)
+    serve.serve_fifo(warm, realtime=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res_b, st = serve.serve_batched(specs, hbm_budget=int(args.hbm_budget_gb * (1 << 30)))
+    wall_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res_f = serve.serve_fifo(specs)
+    wall_f = time.perf_counter() - t0
+    sb, sf = serve.summary(res_b, wall_b), serve.summary(res_f, wall_f)
+    line = {
+        "metric": "serving p99 latency (continuous batching)",
+        "value": None if sb["p99_s"] is None else round(sb["p99_s"], 4),
+        "unit": "s", "n_gpus": 1, "steps": None, "warmup": 2,
+        "ms_per_step": None,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%d Poisson arrivals at %.0f/s of 2-D solves (Rayleigh-Taylor, "
+                               "static drop, impacting drop), edge 64..1024, density ratio "
+                               "3..1000, 500..20000 steps, FP32" % (args.requests, args.rate),
+                   "hbm_budget_gb": args.hbm_budget_gb, "parallelism": "single GPU"},
+        "batched": dict(sb, wall_s=round(wall_b, 2), peak_active=st["peak_active"],
+                        peak_gb=round(st["peak_bytes"] / 2 ** 30, 2)),
+        "fifo": dict(sf, wall_s=round(wall_f, 2)),
+        "unstable_requests": sum(r.status == mplb.EUNSTABLE for r in res_b),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16s"])
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16s", "fp16s_all"])
     ap.add_argument("--nz", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--workload", default="rti3d", choices=["rti3d", "batch", "serve", "splash"],
+                    help="rti3d: the 128x128x512 step (default); batch: 64 uneven domains, "
+                         "batched vs one per launch; serve: request replay; splash: "
+                         "512x512x256 droplet impact in FP64 / FP32 / FP16")
+    ap.add_argument("--splash-steps", type=int, default=200)
+    ap.add_argument("--domains", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--requests", type=int, default=1000)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--hbm-budget-gb", type=float, default=64.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, time a plain device-to-device copy of this "
                          "many MiB (reference kernel for the HBM byte counters)")
@@ -77,6 +293,12 @@ def main():
     from paper_2101_06769_amd import inputs, mplb
 
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
+    if args.workload == "splash":
+        return bench_splash(args)
     if args.copy_probe:
         n = args.copy_probe << 20
         a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
@@ -126,14 +348,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "fp16s": "f16s+f32"}[args.storage],
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16s": "f16s+f32",
+                  "fp16s_all": "f16s"}[args.storage],
         "data": "synthetic",
         "config": {"workload": "3-D Rayleigh-Taylor, D3Q27 cumulant + D3Q27 Allen-Cahn, "
                                "128x128x%d, At 0.5, Re 1000, W 5, %s storage" % (args.nz,
                                                                                 args.storage),
                    "cells": N, "lattice": "D3Q27+D3Q27", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": profiled_traffic(args.storage, args.nz),
                      "kernel": "k_collide", "alg_bytes_per_cell": ab["collide"],
                      "avg_launch_us": round(t_col * 1e6, 2),
                      "phi_pass_avg_launch_us": round(ms_phi / args.steps * 1e3, 2)},

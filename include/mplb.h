@@ -217,6 +217,16 @@ int mplb_batch_set_block(mplb_batch *b, int32_t bx, int32_t by, int32_t bz);
 /* Graph chunk in steps (>= 1), or 0 to launch every step directly. */
 int mplb_batch_set_graph_chunk(mplb_batch *b, int32_t chunk);
 
+/* Autotuner: time `steps` batch steps (after one warm-up step) for each
+ * candidate block shape (candidates = ncand triples bx, by, bz; NULL = a
+ * built-in list), keep the fastest and report it in best[3] and its time per
+ * step.  Timing needs real work, so every attached domain whose window is
+ * open advances by up to ncand * (steps + 1) steps: tune on a copy of the
+ * workload.  Errors: EINVAL (steps < 1, no valid candidate, no attached
+ * domain), EDEVICE. */
+int mplb_batch_tune_block(mplb_batch *b, int32_t steps, const int32_t *candidates, int32_t ncand,
+                          int32_t best[3], double *best_ms_per_step);
+
 /* Attach an initialised solver for the next nsteps batch steps; *slot
  * receives its slot.  The solver must not step on its own while attached.
  * Errors: EINVAL (dimension/storage/stream mismatch), ENOMEM (no free slot

@@ -15,8 +15,13 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmplb.so")
 SOURCES = ["kernels.hip", "api.cpp"]
 
-# hipcc flags: gfx950 only, C++20, and no packed-FP32 instructions.
+# hipcc flags: gfx950 only, C++20, no packed-FP32 instructions, and
+# multiply-add fusion only within one source expression (-ffp-contract=on):
+# the backend would otherwise fuse across statements wherever they share a
+# basic block, so kernels that differ only in control flow (per-lane and
+# row-form addressing, solo and batched launches) would round differently.
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-std=c++20", "-O3", "-fPIC", "-shared",
+               "-ffp-contract=on",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wall", "-Wno-unused-command-line-argument"]
 

@@ -513,6 +513,7 @@ struct mplb_batch {
     dim3 block;
     int grid;
     int chunk;
+    bool row;     // row-form kernels (see row_form_ok)
     long long t;  // batch steps taken
     hipGraphExec_t exec;
     bool have_graph;
@@ -559,6 +560,11 @@ int upload_tables(mplb_batch *b)
                 }
     }
     b->ntiles_host = int(b->tiles.size());
+    bool row = true;
+    for (int i = 0; i < b->capacity; ++i)
+        if (b->slot[i]) row = row && mplb::row_form_ok(b->dim, b->doms[i].g, b->block);
+    if (row != b->row) drop_graph(b);  // a captured graph holds the other kernel
+    b->row = row;
     HIPCHK(hipStreamSynchronize(b->stream));
     HIPCHK(hipMemcpyAsync(b->d_doms, b->doms.data(), sizeof(mplb::BatchDom) * b->capacity,
                           hipMemcpyHostToDevice, b->stream));
@@ -620,6 +626,7 @@ int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t ma
     b->chunk = 16;
     b->t = 0;
     b->have_graph = false;
+    b->row = true;
     const int rc = upload_tables(b);
     if (rc != MPLB_OK) {
         delete b;
@@ -739,8 +746,8 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
                 HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
                 hipError_t e = hipSuccess;
                 for (int k = 0; k < b->chunk && e == hipSuccess; ++k)
-                    e = mplb::launch_batch_step(b->dim, b->storage, b->collision, b->d_doms, b->d_tiles,
-                                                b->d_ntiles, b->d_tbase, k, b->block, b->grid,
+                    e = mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row, b->d_doms,
+                                                b->d_tiles, b->d_ntiles, b->d_tbase, k, b->block, b->grid,
                                                 b->stream);
                 // always end the capture, so that a failure leaves the stream usable
                 const hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
@@ -759,7 +766,7 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
             b->t += b->chunk;
             done += b->chunk;
         } else {
-            HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->collision, b->d_doms, b->d_tiles, b->d_ntiles,
+            HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row, b->d_doms, b->d_tiles, b->d_ntiles,
                                            b->d_tbase, 0, b->block, b->grid, b->stream));
             b->t += 1;
             done += 1;
@@ -776,6 +783,67 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
         s->steps += adv;
         s->cur = int((s->cur + adv) & 1);
     }
+    return MPLB_OK;
+}
+
+int mplb_batch_tune_block(mplb_batch *b, int32_t steps, const int32_t *candidates, int32_t ncand,
+                          int32_t best[3], double *best_ms_per_step)
+{
+    static const int32_t builtin3[] = {64, 4, 1, 64, 2, 2, 128, 2, 1, 128, 1, 2, 256, 1, 1,
+                                       64, 1, 4, 32, 8, 1, 32, 4, 2};
+    static const int32_t builtin2[] = {64, 4, 1, 128, 2, 1, 256, 1, 1, 64, 2, 1, 32, 8, 1,
+                                       16, 16, 1};
+    if (!b || !best || !best_ms_per_step) return fail(MPLB_EINVAL, "batch and outputs are required");
+    if (steps < 1) return fail(MPLB_EINVAL, "steps must be >= 1");
+    bool any = false;
+    for (auto *s : b->slot) any = any || s;
+    if (!any) return fail(MPLB_EINVAL, "no attached domain to time");
+    if (!candidates) {
+        candidates = b->dim == 3 ? builtin3 : builtin2;
+        ncand = b->dim == 3 ? int32_t(sizeof(builtin3) / 12) : int32_t(sizeof(builtin2) / 12);
+    }
+    const dim3 keep = b->block;
+    const int keep_chunk = b->chunk;
+    b->chunk = 0;  // direct launches while tuning: every candidate pays the same launch cost
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(MPLB_EDEVICE, "hipEventCreate failed");
+    }
+    double best_ms = 1e300;
+    int rc = MPLB_OK;
+    for (int i = 0; i < ncand && rc == MPLB_OK; ++i) {
+        const int32_t *c = candidates + 3 * i;
+        if (b->dim == 2 && c[2] != 1) continue;
+        if (mplb_batch_set_block(b, c[0], c[1], c[2]) != MPLB_OK) continue;
+        rc = mplb_batch_step(b, 1);
+        if (rc != MPLB_OK) break;
+        if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = fail(MPLB_EDEVICE, "event"); break; }
+        rc = mplb_batch_step(b, steps);
+        if (rc != MPLB_OK) break;
+        float ms = 0;
+        if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(MPLB_EDEVICE, "event timing failed");
+            break;
+        }
+        if (ms / steps < best_ms) {
+            best_ms = ms / steps;
+            best[0] = c[0];
+            best[1] = c[1];
+            best[2] = c[2];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->chunk = keep_chunk;
+    if (rc == MPLB_OK && best_ms == 1e300) rc = fail(MPLB_EINVAL, "no valid candidate block shape");
+    const int rs = rc == MPLB_OK ? mplb_batch_set_block(b, best[0], best[1], best[2])
+                                 : mplb_batch_set_block(b, keep.x, keep.y, keep.z);
+    if (rc != MPLB_OK) return rc;
+    if (rs != MPLB_OK) return rs;
+    *best_ms_per_step = best_ms;
     return MPLB_OK;
 }
 

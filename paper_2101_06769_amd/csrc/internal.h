@@ -87,7 +87,11 @@ struct BatchTile {
 
 // One step of every active domain: persistent blocks stride over the tile
 // list (*ntiles entries); the batch step index is *tbase + step_off.
-hipError_t launch_batch_step(int dim, int storage, int collision, const BatchDom *doms,
+// True when the row-form kernels apply: block a multiple of 64 wide in x,
+// x periodic, population arrays of fewer than 2^31 elements.
+bool row_form_ok(int dim, const Geom &g, dim3 block);
+// row: every attached domain satisfies row_form_ok with this block.
+hipError_t launch_batch_step(int dim, int storage, int collision, bool row, const BatchDom *doms,
                              const BatchTile *tiles, const int *ntiles, const long long *tbase,
                              int step_off, dim3 block, int grid, hipStream_t stream);
 hipError_t launch_set_i64(long long *ptr, long long v, hipStream_t stream);

@@ -29,6 +29,8 @@
 // separate plane.
 #include <hip/hip_fp16.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace mplb {
@@ -55,6 +57,17 @@ using P32 = Pol<Plain<float>, Plain<float>, float>;
 using P16 = Pol<Half16, Plain<float>, float>;
 using P16A = Pol<Half16, Half16, float>;
 
+// Element x of the row starting at base + off.  The row offset is kept apart
+// from the 32-bit lane offset so that, when it is wavefront-uniform, the
+// address is a scalar base plus a per-lane byte offset.
+template <typename R>
+__device__ __forceinline__ R *lane_ptr(R *base, long long off, int x)
+{
+    using B = typename std::conditional<std::is_const<R>::value, const char, char>::type;
+    return reinterpret_cast<R *>(reinterpret_cast<B *>(base + off) +
+                                 (unsigned)x * (unsigned)sizeof(R));
+}
+
 // Value of direction plane `dir` at `cell`.  Shifted FP16 values decode as
 // w (shift + scale q) with the shift/scale of the cell that stored them
 // (scale 1 when sc is null).
@@ -71,19 +84,93 @@ __device__ __forceinline__ T load_pop(const void *base, long long np, int dir, i
     }
 }
 
-// Store dev + w shift (plain) or dev / (w scale) (shifted).
+// Store dev + w shift (plain) or dev / (w scale) (shifted) as direction a
+// of the cell (row + x).
 template <int D, class S, typename T>
-__device__ __forceinline__ void store_dev(void *base, long long np, int a, int cell, T dev, T shift,
-                                          T scale)
+__device__ __forceinline__ void store_dev(void *base, long long np, int a, int row, int x, T dev,
+                                          T shift, T scale)
 {
     if constexpr (S::shifted) {
         const float w = weight<D, float>(a);
-        static_cast<__half *>(base)[(long long)a * np + cell] =
+        *lane_ptr(static_cast<__half *>(base), (long long)a * np + row, x) =
             __float2half(float(dev) / (w * float(scale)));
     } else {
-        static_cast<typename S::raw *>(base)[(long long)a * np + cell] =
-            typename S::raw(dev + weight<D, T>(a) * shift);
+        __builtin_nontemporal_store(typename S::raw(dev + weight<D, T>(a) * shift),
+                                    lane_ptr(static_cast<typename S::raw *>(base),
+                                             (long long)a * np + row, x));
     }
+}
+
+// Value of direction a held in plane `dir` at cell (row + x); see load_pop.
+template <int D, class S, typename T>
+__device__ __forceinline__ T load_at(const void *base, long long plane, int row, int x, int a,
+                                     const float *sh, const float *sc)
+{
+    if constexpr (S::shifted) {
+        const float q = __half2float(*lane_ptr(static_cast<const __half *>(base), plane + row, x));
+        const float w = weight<D, float>(a);
+        const float s = *lane_ptr(sh, row, x);
+        const float r = sc ? *lane_ptr(sc, row, x) : 1.0f;
+        return T(w * (s + r * q));
+    } else {
+        return T(*lane_ptr(static_cast<const typename S::raw *>(base), plane + row, x));
+    }
+}
+
+// Pre-collision population a at the cell (pull streaming with the boundary
+// rules of pull_src), general form.
+template <int D, class S, typename T>
+__device__ __forceinline__ T pull(const NbLane &n, const void *base, long long np, int a,
+                                  const float *sh, const float *sc)
+{
+    int dir, cell;
+    pull_src<D>(*n.g, n.x, n.y, n.z, a, &dir, &cell);
+    return load_pop<D, S, T>(base, np, dir, cell, a, sh, sc);
+}
+
+// Row form: the y and z rules are wavefront-uniform choices of plane and row
+// read off the wavefront's tables; x wraps per lane.  Offsets are 32-bit
+// element indices (the arrays hold fewer than 2^31 elements).
+template <int D, class S, typename T>
+__device__ __forceinline__ T pull(const NbRow &n, const void *base, long long, int a,
+                                  const float *sh, const float *sc)
+{
+    const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
+    const int ky = 1 - cy, kz = 1 - cz;  // table index of y - cy, z - cz
+    const unsigned by = cy ? 1u << ky : 0u, bz = cz ? 1u << (3 + kz) : 0u;
+    const bool bb = (n.bb & (by | bz)) != 0;
+    const int b = a - ((n.sym & by) ? 6 * cy : 0) - ((n.sym & bz) ? 18 * cz : 0);
+    const int dir = bb ? opposite<D>(a) : b;
+    const int rs = bb ? n.row : n.ry[ky] + n.rz[kz];
+    const int xs = (bb || cx == 0) ? n.x : cx > 0 ? n.xm : n.xp;
+    const unsigned cell = unsigned(rs) + unsigned(xs);
+    const unsigned e = unsigned(dir * n.np) + cell;
+    if constexpr (S::shifted) {
+        const float q = __half2float(static_cast<const __half *>(base)[e]);
+        const float w = weight<D, float>(a);
+        return T(w * (sh[cell] + (sc ? sc[cell] : 1.0f) * q));
+    } else {
+        return T(static_cast<const typename S::raw *>(base)[e]);
+    }
+}
+
+// phi at the stencil neighbour (x + cx, y + cy, z + cz): periodic wrap, or the
+// mirrored first fluid layer beyond walls and symmetry planes.
+template <typename T>
+__device__ __forceinline__ T phi_at(const NbLane &n, const T *phi, int cx, int cy, int cz)
+{
+    const Geom &g = *n.g;
+    const int xx = cx ? stencil_coord(n.x + cx, g.nx, g.bcx) : n.x;
+    const int yy = cy ? stencil_coord(n.y + cy, g.ny, g.bcy) : n.y;
+    const int zz = cz ? stencil_coord(n.z + cz, g.nz, g.bcz) : n.z;
+    return phi[cell_of(g, xx, yy, zz)];
+}
+
+template <typename T>
+__device__ __forceinline__ T phi_at(const NbRow &n, const T *phi, int cx, int cy, int cz)
+{
+    const int xx = cx == 0 ? n.x : cx > 0 ? n.xp : n.xm;
+    return phi[unsigned(n.ry[1 + cy] + n.rz[1 + cz]) + unsigned(xx)];
 }
 
 // Parameters in the arithmetic type.
@@ -130,25 +217,17 @@ struct Cell {
 // Summed over pairs of opposite directions, w (phi(x+c) - phi(x-c)) and
 // w (phi(x+c) + phi(x-c) - 2 phi(x)), so that uniform and mirror-symmetric
 // fields give exactly zero gradient components.
-template <int D, typename T>
-__device__ __forceinline__ void stencil(const Loc &l, const T *__restrict__ phi, Cell<T> &c)
+template <int D, typename T, class NB>
+__device__ __forceinline__ void stencil(const NB &n, const T *__restrict__ phi, Cell<T> &c)
 {
     constexpr int Q = Lat<D>::Q;
-    const Geom &g = *l.g;
-    const int x = l.x, y = l.y, z = l.z;
-    const T p0 = phi[l.me];
+    const T p0 = phi_at(n, phi, 0, 0, 0);
     T gx = 0, gy = 0, gz = 0, lap = 0;
 #pragma unroll
     for (int a = Q / 2 + 1; a < Q; ++a) {
         const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
-        const int xp = cx ? stencil_coord(x + cx, g.nx, g.bcx) : x;
-        const int yp = cy ? stencil_coord(y + cy, g.ny, g.bcy) : y;
-        const int zp = (D == 3 && cz) ? stencil_coord(z + cz, g.nz, g.bcz) : z;
-        const int xm = cx ? stencil_coord(x - cx, g.nx, g.bcx) : x;
-        const int ym = cy ? stencil_coord(y - cy, g.ny, g.bcy) : y;
-        const int zm = (D == 3 && cz) ? stencil_coord(z - cz, g.nz, g.bcz) : z;
-        const T pp = phi[cell_of(g, xp, yp, zp)];
-        const T pm = phi[cell_of(g, xm, ym, zm)];
+        const T pp = phi_at(n, phi, cx, cy, cz);
+        const T pm = phi_at(n, phi, -cx, -cy, -cz);
         const T w = weight<D, T>(a);
         const T d = w * (pp - pm);
         if (cx) gx += T(cx) * d;
@@ -185,24 +264,20 @@ __device__ __forceinline__ void closure(const Phys<T> &ph, Cell<T> &c)
 // pairs of opposite directions (f_a + f_opp for even moments, f_a - f_opp for
 // odd ones) so that the pressure part w p cancels exactly in the odd moments
 // and the velocity part cancels before it reaches the even ones.
-template <int D, class P>
-__device__ __forceinline__ void flow_moments(const Loc &nb, long long np, const Ptrs &p,
+template <int D, class P, class NB>
+__device__ __forceinline__ void flow_moments(const NB &nb, long long np, const Ptrs &p,
                                              Cell<typename P::T> &c)
 {
     using T = typename P::T;
     constexpr int Q = Lat<D>::Q;
-    int dir, cell;
-    pull_src<D>(*nb.g, nb.x, nb.y, nb.z, Q / 2, &dir, &cell);
-    T S0 = load_pop<D, typename P::F, T>(p.Fin, np, dir, cell, Q / 2, p.fp_in, p.fr_in);
+    T S0 = pull<D, typename P::F, T>(nb, p.Fin, np, Q / 2, p.fp_in, p.fr_in);
     T Sx = 0, Sy = 0, Sz = 0, Sxx = 0, Syy = 0, Szz = 0, Sxy = 0, Sxz = 0, Syz = 0;
 #pragma unroll
     for (int a = Q / 2 + 1; a < Q; ++a) {
         const int b = opposite<D>(a);
         const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
-        pull_src<D>(*nb.g, nb.x, nb.y, nb.z, a, &dir, &cell);
-        const T va = load_pop<D, typename P::F, T>(p.Fin, np, dir, cell, a, p.fp_in, p.fr_in);
-        pull_src<D>(*nb.g, nb.x, nb.y, nb.z, b, &dir, &cell);
-        const T vb = load_pop<D, typename P::F, T>(p.Fin, np, dir, cell, b, p.fp_in, p.fr_in);
+        const T va = pull<D, typename P::F, T>(nb, p.Fin, np, a, p.fp_in, p.fr_in);
+        const T vb = pull<D, typename P::F, T>(nb, p.Fin, np, b, p.fp_in, p.fr_in);
         const T sp = va + vb, dm = va - vb;
         S0 += sp;
         if (cx) { Sx += T(cx) * dm; Sxx += sp; }
@@ -230,8 +305,8 @@ __device__ __forceinline__ void velocity(Cell<T> &c)
     c.pstar = c.S0 + T(0.5) * (T(1) / T(3)) * c.U;
 }
 
-template <int D, class P>
-__device__ __forceinline__ void eval_cell(const Loc &nb, long long np,
+template <int D, class P, class NB>
+__device__ __forceinline__ void eval_cell(const NB &nb, long long np,
                                           const Phys<typename P::T> &ph, const Ptrs &p,
                                           Cell<typename P::T> &c)
 {
@@ -362,68 +437,59 @@ __device__ __forceinline__ T source_xi(const Cell<T> &c, int a, T usq, T V, T &g
 
 // ------------------------------------------------------------------ kernels
 
-// Occupancy target of the fused collision: five wavefronts per SIMD for the
-// FP32-arithmetic D3Q27 kernels (at most 96 VGPRs; measured faster than four
-// without the cap), the compiler's choice otherwise.
+// Occupancy target of the fused collision: four wavefronts per SIMD for the
+// FP32-arithmetic D3Q27 kernels (at most 128 VGPRs: measured faster than five,
+// which spills, and than no cap), the compiler's choice otherwise.
 template <int D, class P, int COLL>
 constexpr int collide_waves()
 {
-    return (D == 3 && sizeof(typename P::T) == 4) ? 5 : 1;
+    return (D == 3 && sizeof(typename P::T) == 4) ? 4 : 1;
 }
 
 
 // phi(x) = sum_a g_a(x) over the pulled phase-field populations (Sec. 2.2).
-template <int D, class P>
-__device__ __forceinline__ void phi_body(const Loc &nb, long long np, const Ptrs &p)
+template <int D, class P, class NB>
+__device__ __forceinline__ void phi_body(const NB &nb, long long np, const Ptrs &p)
 {
     using T = typename P::T;
     constexpr int Q = Lat<D>::Q;
     T s = 0;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-        int dir, cell;
-        pull_src<D>(*nb.g, nb.x, nb.y, nb.z, a, &dir, &cell);
-        s += load_pop<D, typename P::G, T>(p.Gin, np, dir, cell, a, p.gp_in, nullptr);
-    }
-    static_cast<T *>(p.phi)[nb.me] = s;
+    for (int a = 0; a < Q; ++a) s += pull<D, typename P::G, T>(nb, p.Gin, np, a, p.gp_in, nullptr);
+    *lane_ptr(static_cast<T *>(p.phi), nb.row, nb.x) = s;
 }
 
-template <int D, class P>
+// x per lane; y and z wavefront-uniform when NB is NbRow.
+template <int D, class P, class NB>
 __device__ __forceinline__ void phi_cell(const Geom &g, const Ptrs &p, int x, int y, int z)
 {
-    const Loc nb{&g, x, y, z, cell_of(g, x, y, z)};
+    const NB nb = make_nb(g, x, y, z, (NB *)nullptr);
     phi_body<D, P>(nb, g.np, p);
 }
 
-template <int D, class P>
-__global__ void __launch_bounds__(256) k_phi(Geom g, Ptrs p)
-{
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z * blockDim.z + threadIdx.z;
-    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
-    phi_cell<D, P>(g, p, x, y, z);
-}
+template <int D, class P, bool ROW>
+__global__ void __launch_bounds__(256) k_phi(Geom g, Ptrs p);
 
 // The fused update of one cell: stencil, closure, flow collision, phase-field
 // collision; post-collision values stored at the cell.
-template <int D, class P, int COLL>
-__device__ __forceinline__ void collide_body(const Loc &nb, const Geom &g,
+template <int D, class P, int COLL, class NB>
+__device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
                                              const Phys<typename P::T> &ph, const Ptrs &p)
 {
     using T = typename P::T;
     constexpr int Q = Lat<D>::Q;
     constexpr T cs2 = T(1) / T(3);
-    const int me = nb.me;
+    const int row = nb.row, xl = nb.x;
 
     Cell<T> c;
     eval_cell<D, P>(nb, g.np, ph, p, c);
+    // Scheduling fences between the phases of the cell update keep the
+    // compiler from hoisting every load of the kernel to its start, which
+    // would hold them all in registers at once (spills, lower occupancy).
+    __builtin_amdgcn_sched_barrier(0);
     const T usq = c.ux * c.ux + c.uy * c.uy + c.uz * c.uz;
     const T V = c.ux * c.Fx + c.uy * c.Fy + c.uz * c.Fz;
     const T rcs2 = c.rho * cs2;
-
-
-
 
     if constexpr (COLL == 0) {
         // second moments of Xi in closed form (4th-order isotropy of the lattice)
@@ -470,25 +536,23 @@ __device__ __forceinline__ void collide_body(const Loc &nb, const Geom &g,
             const T xi = source_xi<D, T>(c, a, usq, V, gam);
             const T dev = rcs2 * hd[a] + T(0.5) * xi;
             if constexpr (P::F::shifted) {
-                store_dev<D, typename P::F, T>(p.Fout, g.np, a, me, dev, c.pstar, rcs2);
+                store_dev<D, typename P::F, T>(p.Fout, g.np, a, row, xl, dev, c.pstar, rcs2);
             } else {
                 const T v = dev + weight<D, T>(a) * c.pstar;
                 fsum += v;
                 __builtin_nontemporal_store(typename P::F::raw(v),
-                    &static_cast<typename P::F::raw *>(p.Fout)[(long long)a * g.np + me]);
+                    lane_ptr(static_cast<typename P::F::raw *>(p.Fout), (long long)a * g.np + row, xl));
             }
         }
         if constexpr (!P::F::shifted)
             __builtin_nontemporal_store(typename P::F::raw((c.S0 + cs2 * c.U) - fsum),
-            &static_cast<typename P::F::raw *>(p.Fout)[(long long)(Q / 2) * g.np + me]);
+                lane_ptr(static_cast<typename P::F::raw *>(p.Fout), (long long)(Q / 2) * g.np + row, xl));
     } else {
         // single relaxation time: f'* = f' - omega (f' - f'_eq) + (1 - omega/2) Xi
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
             const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
-            int dir, cell;
-            pull_src<D>(*nb.g, nb.x, nb.y, nb.z, a, &dir, &cell);
-            const T v = load_pop<D, typename P::F, T>(p.Fin, g.np, dir, cell, a, p.fp_in, p.fr_in);
+            const T v = pull<D, typename P::F, T>(nb, p.Fin, g.np, a, p.fp_in, p.fr_in);
             const T w = weight<D, T>(a);
             const T cu = T(cx) * c.ux + T(cy) * c.uy + T(cz) * c.uz;
             T gam;
@@ -496,14 +560,15 @@ __device__ __forceinline__ void collide_body(const Loc &nb, const Geom &g,
             const T feq_dev = w * rcs2 * (T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
             const T vdev = v - w * c.pstar;
             const T dev = vdev - c.omega * (vdev - feq_dev) + (T(1) - T(0.5) * c.omega) * xi;
-            store_dev<D, typename P::F, T>(p.Fout, g.np, a, me, dev, c.pstar, rcs2);
+            store_dev<D, typename P::F, T>(p.Fout, g.np, a, row, xl, dev, c.pstar, rcs2);
         }
     }
     if constexpr (P::F::shifted) {
-        p.fp_out[me] = float(c.pstar);
-        p.fr_out[me] = float(rcs2);
+        *lane_ptr(p.fp_out, row, xl) = float(c.pstar);
+        *lane_ptr(p.fr_out, row, xl) = float(rcs2);
     }
 
+    __builtin_amdgcn_sched_barrier(0);
     // conservative Allen-Cahn: g* = g + (g_eq - g)/taubar + S_bar (Sec. 2.2).
     // Plain formats take the rest direction as the remainder of sum g* = phi.
     const T nrm = sqrt(c.gx * c.gx + c.gy * c.gy + c.gz * c.gz + T(1e-24));
@@ -514,47 +579,72 @@ __device__ __forceinline__ void collide_body(const Loc &nb, const Geom &g,
     for (int a = 0; a < Q; ++a) {
         if (a == Q / 2 && !P::G::shifted) continue;
         const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
-        int dir, cell;
-        pull_src<D>(*nb.g, nb.x, nb.y, nb.z, a, &dir, &cell);
-        const T v = load_pop<D, typename P::G, T>(p.Gin, g.np, dir, cell, a, p.gp_in, nullptr);
+        const T v = pull<D, typename P::G, T>(nb, p.Gin, g.np, a, p.gp_in, nullptr);
         const T w = weight<D, T>(a);
         const T cu = T(cx) * c.ux + T(cy) * c.uy + T(cz) * c.uz;
         const T geq = w * c.phi * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
         const T cn = T(cx) * nx + T(cy) * ny + T(cz) * nz;
         const T gout = v + (geq - v) * ph.inv_tpb + w * cn * src;
         if constexpr (P::G::shifted) {
-            store_dev<D, typename P::G, T>(p.Gout, g.np, a, me, gout - w * c.phi, c.phi, T(1));
+            store_dev<D, typename P::G, T>(p.Gout, g.np, a, row, xl, gout - w * c.phi, c.phi,
+                                           T(1));
         } else {
             gsum += gout;
             __builtin_nontemporal_store(typename P::G::raw(gout),
-                &static_cast<typename P::G::raw *>(p.Gout)[(long long)a * g.np + me]);
+                lane_ptr(static_cast<typename P::G::raw *>(p.Gout), (long long)a * g.np + row, xl));
         }
     }
     if constexpr (!P::G::shifted)
         __builtin_nontemporal_store(typename P::G::raw(c.phi - gsum),
-            &static_cast<typename P::G::raw *>(p.Gout)[(long long)(Q / 2) * g.np + me]);
-    if constexpr (P::G::shifted) p.gp_out[me] = float(c.phi);
-
-
+            lane_ptr(static_cast<typename P::G::raw *>(p.Gout), (long long)(Q / 2) * g.np + row, xl));
+    if constexpr (P::G::shifted) *lane_ptr(p.gp_out, row, xl) = float(c.phi);
 }
 
-template <int D, class P, int COLL>
+template <int D, class P, int COLL, class NB>
 __device__ __forceinline__ void collide_cell(const Geom &g, const Phys<typename P::T> &ph,
                                              const Ptrs &p, int x, int y, int z)
 {
-    const Loc nb{&g, x, y, z, cell_of(g, x, y, z)};
+    const NB nb = make_nb(g, x, y, z, (NB *)nullptr);
     collide_body<D, P, COLL>(nb, g, ph, p);
 }
 
-template <int D, class P, int COLL>
+template <bool ROW>
+using NbOf = typename std::conditional<ROW, NbRow, NbLane>::type;
+
+// Thread -> cell for a block starting at (x0, y0, z0).  ROW: the block is a
+// multiple of 64 wide in x, so each wavefront lies in one x-row and y, z are
+// taken from its first lane as wavefront-uniform values.
+template <bool ROW>
+__device__ __forceinline__ void thread_cell(int x0, int y0, int z0, int &x, int &y, int &z)
+{
+    x = x0 + int(threadIdx.x);
+    y = y0 + int(threadIdx.y);
+    z = z0 + int(threadIdx.z);
+    if constexpr (ROW) {
+        y = __builtin_amdgcn_readfirstlane(y);
+        z = __builtin_amdgcn_readfirstlane(z);
+    }
+}
+
+template <int D, class P, bool ROW>
+__global__ void __launch_bounds__(256) k_phi(Geom g, Ptrs p)
+{
+    int x, y, z;
+    thread_cell<ROW>(blockIdx.x * blockDim.x, blockIdx.y * blockDim.y, blockIdx.z * blockDim.z, x,
+                     y, z);
+    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+    phi_cell<D, P, NbOf<ROW>>(g, p, x, y, z);
+}
+
+template <int D, class P, int COLL, bool ROW>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(collide_waves<D, P, COLL>())))
 k_collide(Geom g, Phys<typename P::T> ph, Ptrs p)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z * blockDim.z + threadIdx.z;
+    int x, y, z;
+    thread_cell<ROW>(blockIdx.x * blockDim.x, blockIdx.y * blockDim.y, blockIdx.z * blockDim.z, x,
+                     y, z);
     if (x >= g.nx || y >= g.ny || z >= g.nz) return;
-    collide_cell<D, P, COLL>(g, ph, p, x, y, z);
+    collide_cell<D, P, COLL, NbOf<ROW>>(g, ph, p, x, y, z);
 }
 
 // Equilibrium initial state, computed in FP64 for every storage format and
@@ -572,7 +662,7 @@ __global__ void __launch_bounds__(256) k_init(Geom g, PhysD ph, Ptrs p, const do
     const int me = cell_of(g, x, y, z);
     const long long N = (long long)g.nx * g.ny * g.nz;
     Cell<double> c;
-    stencil<D, double>(Loc{&g, x, y, z, cell_of(g, x, y, z)}, dphi, c);
+    stencil<D, double>(make_nb(g, x, y, z, (NbLane *)nullptr), dphi, c);
     closure<D, double>(to_phys<double>(ph), c);
     const double ux = du[me], uy = du[N + me], uz = D == 3 ? du[2 * N + me] : 0.0;
     const double h = 0.5 * c.irho;
@@ -697,7 +787,7 @@ __global__ void __launch_bounds__(256) k_field(Geom g, Phys<typename P::T> ph, P
     const int z = blockIdx.z * blockDim.z + threadIdx.z;
     if (x >= g.nx || y >= g.ny || z >= g.nz) return;
     Cell<T> c;
-    const Loc nb{&g, x, y, z, cell_of(g, x, y, z)};
+    const NbLane nb = make_nb(g, x, y, z, (NbLane *)nullptr);
     eval_cell<D, P>(nb, g.np, ph, p, c);
     T v = field == 0 ? c.phi : field == 1 ? c.rho : field == 2 ? c.ux : field == 3 ? c.uy
         : field == 4 ? c.uz : c.pstar;
@@ -733,7 +823,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_partial(Geom g, Phys<typ
          i += (long long)gridDim.x * RED_THREADS) {
         const int x = int(i % g.nx), y = int((i / g.nx) % g.ny), z = int(i / ((long long)g.nx * g.ny));
         Cell<T> c;
-        const Loc nb{&g, x, y, z, cell_of(g, x, y, z)};
+        const NbLane nb = make_nb(g, x, y, z, (NbLane *)nullptr);
         eval_cell<D, P>(nb, g.np, ph, p, c);
         const double rho = double(c.rho);
         const double ux = double(c.ux), uy = double(c.uy), uz = double(c.uz);
@@ -812,7 +902,7 @@ __device__ __forceinline__ Ptrs batch_ptrs(const BatchDom &d, int in)
     return p;
 }
 
-template <int D, class P, int COLL, bool PHI>
+template <int D, class P, int COLL, bool PHI, bool ROW>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(PHI ? 1 : collide_waves<D, P, COLL>()))) kb_step(const BatchDom *__restrict__ doms,
                                                const BatchTile *__restrict__ tiles,
@@ -826,13 +916,14 @@ __attribute__((amdgpu_waves_per_eu(PHI ? 1 : collide_waves<D, P, COLL>()))) kb_s
         const BatchTile tl = tiles[ti];
         const BatchDom &d = doms[tl.dom];
         if (t < d.first || t >= d.last) continue;
-        const int x = tl.x0 + threadIdx.x, y = tl.y0 + threadIdx.y, z = tl.z0 + threadIdx.z;
+        int x, y, z;
+        thread_cell<ROW>(tl.x0, tl.y0, tl.z0, x, y, z);
         if (x >= d.g.nx || y >= d.g.ny || z >= d.g.nz) continue;
         const Ptrs p = batch_ptrs(d, int((t - d.first) & 1));
         if constexpr (PHI)
-            phi_cell<D, P>(d.g, p, x, y, z);
+            phi_cell<D, P, NbOf<ROW>>(d.g, p, x, y, z);
         else
-            collide_cell<D, P, COLL>(d.g, to_phys<T>(d.ph), p, x, y, z);
+            collide_cell<D, P, COLL, NbOf<ROW>>(d.g, to_phys<T>(d.ph), p, x, y, z);
     }
 }
 
@@ -868,10 +959,23 @@ static hipError_t dispatch(const Ctx &c, Fn &&fn)
     return hipErrorInvalidValue;
 }
 
+// Row-form addressing: every wavefront inside one x-row of the block, x
+// periodic, population arrays of fewer than 2^31 elements.
+bool row_form_ok(int dim, const Geom &g, dim3 block)
+{
+    const long long Q = dim == 2 ? 9 : 27;
+    return block.x % 64 == 0 && g.bcx == BC_PER && Q * g.np < (1ll << 31);
+}
+
+static bool row_form(const Ctx &c) { return row_form_ok(c.dim, c.g, c.block); }
+
 hipError_t launch_phi(const Ctx &c)
 {
     return dispatch(c, [&]<int D, class P>() {
-        hipLaunchKernelGGL((k_phi<D, P>), grid_for(c), c.block, 0, c.stream, c.g, c.p);
+        if (row_form(c))
+            hipLaunchKernelGGL((k_phi<D, P, true>), grid_for(c), c.block, 0, c.stream, c.g, c.p);
+        else
+            hipLaunchKernelGGL((k_phi<D, P, false>), grid_for(c), c.block, 0, c.stream, c.g, c.p);
         return hipGetLastError();
     });
 }
@@ -879,12 +983,20 @@ hipError_t launch_phi(const Ctx &c)
 hipError_t launch_collide(const Ctx &c)
 {
     return dispatch(c, [&]<int D, class P>() {
-        if (c.ph.collision == 0)
-            hipLaunchKernelGGL((k_collide<D, P, 0>), grid_for(c), c.block, 0, c.stream, c.g,
-                               to_phys<typename P::T>(c.ph), c.p);
+        using T = typename P::T;
+        const bool row = row_form(c);
+        if (c.ph.collision == 0 && row)
+            hipLaunchKernelGGL((k_collide<D, P, 0, true>), grid_for(c), c.block, 0, c.stream, c.g,
+                               to_phys<T>(c.ph), c.p);
+        else if (c.ph.collision == 0)
+            hipLaunchKernelGGL((k_collide<D, P, 0, false>), grid_for(c), c.block, 0, c.stream,
+                               c.g, to_phys<T>(c.ph), c.p);
+        else if (row)
+            hipLaunchKernelGGL((k_collide<D, P, 1, true>), grid_for(c), c.block, 0, c.stream, c.g,
+                               to_phys<T>(c.ph), c.p);
         else
-            hipLaunchKernelGGL((k_collide<D, P, 1>), grid_for(c), c.block, 0, c.stream, c.g,
-                               to_phys<typename P::T>(c.ph), c.p);
+            hipLaunchKernelGGL((k_collide<D, P, 1, false>), grid_for(c), c.block, 0, c.stream,
+                               c.g, to_phys<T>(c.ph), c.p);
         return hipGetLastError();
     });
 }
@@ -936,7 +1048,7 @@ hipError_t launch_field(const Ctx &c, int field, double *dst)
     });
 }
 
-hipError_t launch_batch_step(int dim, int storage, int collision, const BatchDom *doms,
+hipError_t launch_batch_step(int dim, int storage, int collision, bool row, const BatchDom *doms,
                              const BatchTile *tiles, const int *ntiles, const long long *tbase,
                              int step_off, dim3 block, int grid, hipStream_t stream)
 {
@@ -944,16 +1056,26 @@ hipError_t launch_batch_step(int dim, int storage, int collision, const BatchDom
     c.dim = dim;
     c.storage = storage;
     return dispatch(c, [&]<int D, class P>() {
-        hipLaunchKernelGGL((kb_step<D, P, 0, true>), dim3(grid), block, 0, stream, doms, tiles,
-                           ntiles, tbase, step_off);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        if (collision == 0)
-            hipLaunchKernelGGL((kb_step<D, P, 0, false>), dim3(grid), block, 0, stream, doms,
+        if (row)
+            hipLaunchKernelGGL((kb_step<D, P, 0, true, true>), dim3(grid), block, 0, stream, doms,
                                tiles, ntiles, tbase, step_off);
         else
-            hipLaunchKernelGGL((kb_step<D, P, 1, false>), dim3(grid), block, 0, stream, doms,
+            hipLaunchKernelGGL((kb_step<D, P, 0, true, false>), dim3(grid), block, 0, stream, doms,
                                tiles, ntiles, tbase, step_off);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (collision == 0 && row)
+            hipLaunchKernelGGL((kb_step<D, P, 0, false, true>), dim3(grid), block, 0, stream, doms,
+                               tiles, ntiles, tbase, step_off);
+        else if (collision == 0)
+            hipLaunchKernelGGL((kb_step<D, P, 0, false, false>), dim3(grid), block, 0, stream,
+                               doms, tiles, ntiles, tbase, step_off);
+        else if (row)
+            hipLaunchKernelGGL((kb_step<D, P, 1, false, true>), dim3(grid), block, 0, stream, doms,
+                               tiles, ntiles, tbase, step_off);
+        else
+            hipLaunchKernelGGL((kb_step<D, P, 1, false, false>), dim3(grid), block, 0, stream,
+                               doms, tiles, ntiles, tbase, step_off);
         return hipGetLastError();
     });
 }

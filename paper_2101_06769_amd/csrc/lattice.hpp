@@ -93,10 +93,67 @@ __device__ __forceinline__ void pull_src(const Geom &g, int x, int y, int z, int
     }
 }
 
-// The cell a thread works on.
-struct Loc {
+// Neighbourhood of the cell a thread works on, general form: every lane
+// applies the boundary rules to its own coordinates, for any block shape.
+// row = (z ny + y) nx is the offset of the cell's x-row, me = row + x.
+struct NbLane {
     const Geom *g;
-    int x, y, z, me;
+    int x, y, z, row, me;
 };
+
+// Row form, for blocks a multiple of 64 cells wide in x on lattices periodic
+// in x whose population arrays have fewer than 2^31 elements: the lanes of a
+// wavefront then share y and z, so every decision along y and z (periodic
+// wrap, bounce-back, mirroring) is wavefront-uniform.  It is taken once per
+// wavefront into small tables: ry[k] = y'(y + k) nx and rz[k] = z'(z + k) nx ny
+// for k = -1, 0, 1, with y', z' the wrapped coordinate on periodic axes and
+// the cell's own one where the neighbour lies beyond a wall or symmetry plane
+// (which is also the mirrored ghost of the phi stencil); bit k + 1 of bb and
+// sym (y) and bit k + 4 (z) flag links through a wall or a symmetry plane.
+// Lanes differ only in x, through xm = x - 1 and xp = x + 1 (wrapped).
+struct NbRow {
+    const Geom *g;
+    int x, y, z, row, me;
+    int xm, xp;
+    int np;
+    int ry[3], rz[3];
+    unsigned bb, sym;
+};
+
+__device__ __forceinline__ NbLane make_nb(const Geom &g, int x, int y, int z, NbLane *)
+{
+    const int row = (z * g.ny + y) * g.nx;
+    return NbLane{&g, x, y, z, row, row + x};
+}
+
+// y and z must be the same in every active lane of the wavefront.
+__device__ __forceinline__ NbRow make_nb(const Geom &g, int x, int y, int z, NbRow *)
+{
+    NbRow n;
+    n.g = &g;
+    n.x = x;
+    n.y = y;
+    n.z = z;
+    n.row = (z * g.ny + y) * g.nx;
+    n.me = n.row + x;
+    n.xm = x == 0 ? g.nx - 1 : x - 1;
+    n.xp = x == g.nx - 1 ? 0 : x + 1;
+    n.np = int(g.np);
+    n.bb = 0;
+    n.sym = 0;
+    const int nxny = g.nx * g.ny;
+#pragma unroll
+    for (int k = -1; k <= 1; ++k) {
+        const int yy = y + k, zz = z + k;
+        const bool oy = (unsigned)yy >= (unsigned)g.ny, oz = (unsigned)zz >= (unsigned)g.nz;
+        n.ry[k + 1] = (!oy ? yy : g.bcy == BC_PER ? yy - k * g.ny : y) * g.nx;
+        n.rz[k + 1] = (!oz ? zz : g.bcz == BC_PER ? zz - k * g.nz : z) * nxny;
+        n.bb |= ((oy && g.bcy == BC_WALL) ? 1u << (k + 1) : 0u) |
+                ((oz && g.bcz == BC_WALL) ? 1u << (k + 4) : 0u);
+        n.sym |= ((oy && g.bcy == BC_SYM) ? 1u << (k + 1) : 0u) |
+                 ((oz && g.bcz == BC_SYM) ? 1u << (k + 4) : 0u);
+    }
+    return n;
+}
 
 }  // namespace mplb

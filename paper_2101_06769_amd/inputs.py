@@ -226,11 +226,12 @@ def static_droplet(dim=2, n=(64, 64, 1), R=12.0, sigma=1e-3, rho_ratio=20.0, nu=
     return Case("static_droplet", params, phi, u, p, steps, dict(R=R, sigma=sigma))
 
 
-def impacting_droplet2d(n=256, D=None, U0=0.05, Re=200.0, We=220.0, W=4.0, M=0.1, steps=2000):
+def impacting_droplet2d(n=256, D=None, U0=0.05, Re=200.0, We=220.0, W=4.0, M=0.1, steps=2000,
+                        rho_ratio=1000.0):
     """2-D droplet impact on a liquid sheet in an n x n box: walls top and
     bottom, periodic sides, sheet of depth 0.1 D."""
     D = n / 8.0 if D is None else D
-    sp = splash_parameters(D, U0, Re, We)
+    sp = splash_parameters(D, U0, Re, We, rho_ratio=rho_ratio)
     params = dict(dim=2, n=(n, n, 1), bc=(BC_PERIODIC, BC_WALL, BC_PERIODIC), rho_h=1.0,
                   rho_l=sp["rho_l"], nu_h=sp["nu_h"], nu_l=sp["nu_l"], W=W, M=M,
                   sigma=sp["sigma"], g=(0.0, 0.0, 0.0))
@@ -283,3 +284,52 @@ def population_noise(Q, n, seed, amp):
     rng = np.random.default_rng(seed)
     nx, ny, nz = n
     return amp * rng.uniform(-1.0, 1.0, size=(Q, nz, ny, nx))
+
+
+def serving_spec(seed=1, count=1000, rate=20.0, edge_range=(64, 1024), steps_range=(500, 20000),
+                 rho_ratio_range=(3.0, 1000.0)):
+    """Seeded request stream for the serving workload: Poisson arrivals at
+    `rate` per second; each request is a 2-D solve of one of three types
+    (Rayleigh-Taylor, static drop, impacting drop, equally likely) on an
+    edge x edge lattice with the edge, the density ratio and the number of
+    steps log-uniform in their ranges.  Per type: Rayleigh-Taylor Re
+    log-uniform in [100, 1000]; static drop R = edge/8, sigma log-uniform in
+    [1e-4, 1e-2]; impacting drop D = edge/8, U0 = 0.05, Re log-uniform in
+    [100, 1000], We log-uniform in [100, 2000]; W = 4, M = 0.1.
+    Returns a list of dicts (id, arrival, kind, edge, rho_ratio, steps, ...);
+    `serving_case` builds the fields of one."""
+    rng = np.random.default_rng(seed)
+
+    def logu(lo, hi):
+        return float(math.exp(rng.uniform(math.log(lo), math.log(hi))))
+
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        kind = ("rti", "static_drop", "impacting_drop")[int(rng.integers(0, 3))]
+        spec = dict(id=i, arrival=t, kind=kind, edge=int(round(logu(*edge_range))),
+                    rho_ratio=logu(*rho_ratio_range), steps=int(round(logu(*steps_range))))
+        if kind == "rti":
+            spec["Re"] = logu(100.0, 1000.0)
+        elif kind == "static_drop":
+            spec["sigma"] = logu(1e-4, 1e-2)
+        else:
+            spec["Re"] = logu(100.0, 1000.0)
+            spec["We"] = logu(100.0, 2000.0)
+        out.append(spec)
+    return out
+
+
+def serving_case(spec):
+    """The Case of one serving request (see serving_spec)."""
+    e, r = spec["edge"], spec["rho_ratio"]
+    if spec["kind"] == "rti":
+        At = (r - 1.0) / (r + 1.0)
+        return rti2d(nx=e, ny=e, At=At, Re=spec["Re"], W=4.0, M=0.1, amp=0.05 * e,
+                     steps=spec["steps"])
+    if spec["kind"] == "static_drop":
+        return static_droplet(dim=2, n=(e, e, 1), R=e / 8.0, sigma=spec["sigma"], rho_ratio=r,
+                              nu=0.1, W=4.0, M=0.1, steps=spec["steps"])
+    return impacting_droplet2d(n=e, D=e / 8.0, U0=0.05, Re=spec["Re"], We=spec["We"], W=4.0,
+                               M=0.1, steps=spec["steps"], rho_ratio=r)

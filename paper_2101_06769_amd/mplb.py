@@ -93,6 +93,7 @@ def load_library():
                                       ctypes.c_int64, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     lib.mplb_batch_set_block.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.mplb_batch_set_graph_chunk.argtypes = [vp, ctypes.c_int32]
+    lib.mplb_batch_tune_block.argtypes = [vp, ctypes.c_int32, i32p, ctypes.c_int32, i32p, dp]
     lib.mplb_batch_attach.argtypes = [vp, vp, ctypes.c_int64, i32p]
     lib.mplb_batch_detach.argtypes = [vp, ctypes.c_int32]
     lib.mplb_batch_step.argtypes = [vp, ctypes.c_int64]
@@ -308,6 +309,18 @@ class Batch:
 
     def set_graph_chunk(self, chunk):
         check(self._lib.mplb_batch_set_graph_chunk(self.h, int(chunk)))
+
+    def tune_block(self, steps=4, candidates=None):
+        """Fastest block shape for the attached domains (advances them; tune a copy)."""
+        best = (ctypes.c_int32 * 3)()
+        ms = ctypes.c_double()
+        if candidates:
+            arr = (ctypes.c_int32 * (3 * len(candidates)))(*[int(v) for c in candidates for v in c])
+            n = len(candidates)
+        else:
+            arr, n = None, 0
+        check(self._lib.mplb_batch_tune_block(self.h, int(steps), arr, n, best, ctypes.byref(ms)))
+        return tuple(best), ms.value
 
     def attach(self, solver, nsteps):
         slot = ctypes.c_int32()

@@ -122,3 +122,26 @@ def test_attached_solver_cannot_step_alone():
         b.attach(s, 3)
     b.detach(slot)
     s.step(1)
+
+
+def test_batch_tuner_picks_a_valid_shape_and_results_stay_bitwise():
+    cases = small_batch_cases(count=3, seed=21)
+    b = mplb.Batch(3, "fp32", capacity=4, max_tiles=1 << 14)
+    tune = [solver_for(c, stream=b.stream) for c in cases]
+    for s in tune:
+        b.attach(s, 10 ** 6)
+    best, ms = b.tune_block(steps=2, candidates=[(64, 4, 1), (32, 4, 2), (128, 2, 1)])
+    assert tuple(best) in [(64, 4, 1), (32, 4, 2), (128, 2, 1)] and ms > 0
+    for sl in list(b.members):
+        b.detach(sl)
+    steps = 7
+    solvers = [solver_for(c, stream=b.stream) for c in cases]
+    for s in solvers:
+        b.attach(s, steps)
+    b.step(steps)
+    for c, s in zip(cases, solvers):
+        ref = solver_for(c)
+        ref.step(steps)
+        fa, ga = state(ref)
+        fb, gb = state(s)
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb)

@@ -65,3 +65,26 @@ def test_batch_generator_is_seeded_and_uneven():
         nx, ny, nz = c.params["n"]
         assert nz == 4 * nx and nx == ny
         assert 0.1 <= c.meta["At"] <= 0.9 and 100 <= c.meta["Re"] <= 3000
+
+
+def test_serving_spec_is_seeded_and_within_ranges():
+    a = inputs.serving_spec(seed=1, count=400)
+    b = inputs.serving_spec(seed=1, count=400)
+    assert a == b
+    arr = np.array([s["arrival"] for s in a])
+    assert np.all(np.diff(arr) > 0)
+    # Poisson at 20/s: mean gap 0.05 s
+    assert abs(np.diff(arr).mean() - 0.05) < 0.01
+    for s in a:
+        assert 64 <= s["edge"] <= 1024 and 500 <= s["steps"] <= 20000
+        assert 3.0 <= s["rho_ratio"] <= 1000.0
+        assert s["kind"] in ("rti", "static_drop", "impacting_drop")
+    kinds = {k: sum(s["kind"] == k for s in a) for k in ("rti", "static_drop", "impacting_drop")}
+    assert min(kinds.values()) > 100
+    # each kind builds a 2-D case of the requested size and density ratio
+    for kind in kinds:
+        s = next(x for x in a if x["kind"] == kind and x["edge"] < 128)
+        c = inputs.serving_case(s)
+        assert c.params["dim"] == 2 and c.params["n"] == (s["edge"], s["edge"], 1)
+        assert abs(c.params["rho_h"] / c.params["rho_l"] - s["rho_ratio"]) < 1e-9 * s["rho_ratio"]
+        assert 0.0 <= c.phi.min() and c.phi.max() <= 1.0
