@@ -176,9 +176,18 @@ def bench_splash(args):
     N = case.ncells
     out = {}
     ref = None
-    for storage in ("fp64", "fp32", "fp16s", "fp16s_all"):
-        s = mplb.Solver(case.params, storage=storage)
-        s.init(case.phi, case.u, case.p)
+    rng = np.random.default_rng(7)
+    # "fp64_floor": FP64 again, from inputs carrying one FP32 rounding
+    # (relative 2^-24): the method's own sensitivity, the error any FP32
+    # state would show against FP64 without any arithmetic difference
+    for storage in ("fp64", "fp64_floor", "fp32", "fp16s", "fp16s_all"):
+        s = mplb.Solver(case.params, storage=storage.split("_floor")[0])
+        if storage == "fp64_floor":
+            def pert(a):
+                return a * (1.0 + 2.0 ** -24 * rng.uniform(-1.0, 1.0, a.shape))
+            s.init(np.clip(pert(case.phi), 0.0, 1.0), pert(case.u), pert(case.p))
+        else:
+            s.init(case.phi, case.u, case.p)
         s.step(5)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -191,7 +200,8 @@ def bench_splash(args):
         red, rc = s.reduce()
         rec = {"mlups": round(N * args.splash_steps / (ms / 1e3) / 1e6, 1),
                "ms_per_step": round(ms / args.splash_steps, 4),
-               "alg_GBs": round(ALG_BYTES[(storage, 3)]["method"] * N * args.splash_steps /
+               "alg_GBs": round(ALG_BYTES[(storage.split("_floor")[0], 3)]["method"] * N *
+                                args.splash_steps /
                                 (ms / 1e3) / 1e9, 1),
                "status": "ok" if rc == mplb.OK else "unstable",
                "phase_mass_rel_drift": abs(red[0] - case.phi.sum()) / case.phi.sum()}

@@ -420,32 +420,59 @@ __device__ __forceinline__ void rebuild(T ux, T uy, T uz, T dxx, T dyy, T dzz, T
     }
 }
 
+// c_a . v with the zero components of c_a dropped at compile time (a is a
+// constant once the direction loops are unrolled; 0 * v cannot be folded
+// away under IEEE rules, so the products are never formed).
+template <int D, typename T>
+__device__ __forceinline__ T cdot(int a, T vx, T vy, T vz)
+{
+    const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
+    T s = T(0);
+    bool any = false;
+    if (cx) { s = cx > 0 ? vx : -vx; any = true; }
+    if (cy) { const T t = cy > 0 ? vy : -vy; s = any ? s + t : t; any = true; }
+    if (cz) { const T t = cz > 0 ? vz : -vz; s = any ? s + t : t; any = true; }
+    return s;
+}
+
+// Second-order equilibrium weights of a direction a and its opposite,
+// Gamma = w (1 - 3/2 u^2 + 9/2 (c.u)^2) +- 3 w c.u (Appendix A), from
+// base = 1 - 3/2 u^2 and cu = c_a . u.
+template <typename T>
+__device__ __forceinline__ void gamma_pair(T w, T base, T cu, T &ga, T &gb)
+{
+    const T e = w * (base + T(4.5) * cu * cu);
+    const T o = T(3) * w * cu;
+    ga = e + o;
+    gb = e - o;
+}
+
 // Source term of the flow populations (Sec. 2.3, dilatation term dropped):
 // Xi_a = cs^2 (Gamma_a - w_a)(c_a - u).grad(rho) + Gamma_a (c_a - u).F,
 // Gamma_a = f_eq_a / rho (second-order Hermite equilibrium, Appendix A).
 template <int D, typename T>
 __device__ __forceinline__ T source_xi(const Cell<T> &c, int a, T usq, T V, T &gam)
 {
-    const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
     const T w = weight<D, T>(a);
-    const T cu = T(cx) * c.ux + T(cy) * c.uy + T(cz) * c.uz;
+    const T cu = cdot<D>(a, c.ux, c.uy, c.uz);
     gam = w * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
-    const T cg = T(cx) * c.drx + T(cy) * c.dry + T(cz) * c.drz - c.U;
-    const T cf = T(cx) * c.Fx + T(cy) * c.Fy + T(cz) * c.Fz - V;
+    const T cg = cdot<D>(a, c.drx, c.dry, c.drz) - c.U;
+    const T cf = cdot<D>(a, c.Fx, c.Fy, c.Fz) - V;
     return (T(1) / T(3)) * (gam - w) * cg + gam * cf;
 }
 
 // ------------------------------------------------------------------ kernels
 
 // Occupancy target of the fused collision: four wavefronts per SIMD for the
-// FP32-arithmetic D3Q27 kernels (at most 128 VGPRs: measured faster than five,
-// which spills, and than no cap), the compiler's choice otherwise.
+// D3Q27 kernels with FP32 arithmetic and plain FP32 flow storage (at most 128
+// VGPRs: measured faster than five, which spills, and than no cap); the
+// compiler's choice otherwise (the FP16 formats gather a shift and a scale
+// with every population and spill under the cap).
 template <int D, class P, int COLL>
 constexpr int collide_waves()
 {
-    return (D == 3 && sizeof(typename P::T) == 4) ? 4 : 1;
+    return (D == 3 && sizeof(typename P::T) == 4 && !P::F::shifted) ? 4 : 1;
 }
-
 
 // phi(x) = sum_a g_a(x) over the pulled phase-field populations (Sec. 2.2).
 template <int D, class P, class NB>
@@ -525,16 +552,13 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
             rebuild<D, T>(c.ux, c.uy, T(0), T(0.5) * A, T(-0.5) * A, T(0), om1 * Pxy, T(0), T(0),
                           hd);
         }
-        // f'* = rho cs^2 (h* - w) + w p* + Xi/2.  Plain formats take the rest
-        // direction as the remainder of sum f'* = sum f' + sum Xi, so the
-        // zeroth moment does not drift with the rounding of the weights.
+        // f'* = rho cs^2 (h* - w) + w p* + Xi/2, a direction and its opposite
+        // together (c.u, c.grad(rho), c.F change sign).  Plain formats take
+        // the rest direction as the remainder of sum f'* = sum f' + sum Xi, so
+        // the zeroth moment does not drift with the rounding of the weights.
+        const T base = T(1) - T(1.5) * usq;
         T fsum = 0;
-#pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            if (a == Q / 2 && !P::F::shifted) continue;
-            T gam;
-            const T xi = source_xi<D, T>(c, a, usq, V, gam);
-            const T dev = rcs2 * hd[a] + T(0.5) * xi;
+        auto emit = [&](int a, T dev) {
             if constexpr (P::F::shifted) {
                 store_dev<D, typename P::F, T>(p.Fout, g.np, a, row, xl, dev, c.pstar, rcs2);
             } else {
@@ -543,10 +567,31 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
                 __builtin_nontemporal_store(typename P::F::raw(v),
                     lane_ptr(static_cast<typename P::F::raw *>(p.Fout), (long long)a * g.np + row, xl));
             }
+        };
+#pragma unroll
+        for (int a = Q / 2 + 1; a < Q; ++a) {
+            const int b = opposite<D>(a);
+            const T w = weight<D, T>(a);
+            const T cu = cdot<D>(a, c.ux, c.uy, c.uz);
+            const T cg = cdot<D>(a, c.drx, c.dry, c.drz);
+            const T cf = cdot<D>(a, c.Fx, c.Fy, c.Fz);
+            T ga, gb;
+            gamma_pair(w, base, cu, ga, gb);
+            // Xi = cs^2 (Gamma - w)(c.grad(rho) - U) + Gamma (c.F - V)
+            const T xa = cs2 * (ga - w) * (cg - c.U) + ga * (cf - V);
+            const T xb = -(cs2 * (gb - w) * (cg + c.U) + gb * (cf + V));
+            emit(a, rcs2 * hd[a] + T(0.5) * xa);
+            emit(b, rcs2 * hd[b] + T(0.5) * xb);
         }
-        if constexpr (!P::F::shifted)
+        if constexpr (P::F::shifted) {
+            constexpr int a0 = Q / 2;
+            const T w0 = weight<D, T>(a0);
+            const T g0 = w0 * base;
+            emit(a0, rcs2 * hd[a0] + T(0.5) * (-(cs2 * (g0 - w0) * c.U + g0 * V)));
+        } else {
             __builtin_nontemporal_store(typename P::F::raw((c.S0 + cs2 * c.U) - fsum),
                 lane_ptr(static_cast<typename P::F::raw *>(p.Fout), (long long)(Q / 2) * g.np + row, xl));
+        }
     } else {
         // single relaxation time: f'* = f' - omega (f' - f'_eq) + (1 - omega/2) Xi
 #pragma unroll
@@ -574,29 +619,40 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
     const T nrm = sqrt(c.gx * c.gx + c.gy * c.gy + c.gz * c.gz + T(1e-24));
     const T nx = c.gx / nrm, ny = c.gy / nrm, nz = c.gz / nrm;
     const T src = ph.src_pre * ph.four_W * c.phi * (T(1) - c.phi);
+    // g_eq = phi Gamma: a direction and its opposite together.
+    const T gbase = T(1) - T(1.5) * usq;
     T gsum = 0;
-#pragma unroll
-    for (int a = 0; a < Q; ++a) {
-        if (a == Q / 2 && !P::G::shifted) continue;
-        const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
-        const T v = pull<D, typename P::G, T>(nb, p.Gin, g.np, a, p.gp_in, nullptr);
-        const T w = weight<D, T>(a);
-        const T cu = T(cx) * c.ux + T(cy) * c.uy + T(cz) * c.uz;
-        const T geq = w * c.phi * (T(1) + T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq);
-        const T cn = T(cx) * nx + T(cy) * ny + T(cz) * nz;
-        const T gout = v + (geq - v) * ph.inv_tpb + w * cn * src;
+    auto gemit = [&](int a, T gout) {
         if constexpr (P::G::shifted) {
-            store_dev<D, typename P::G, T>(p.Gout, g.np, a, row, xl, gout - w * c.phi, c.phi,
-                                           T(1));
+            store_dev<D, typename P::G, T>(p.Gout, g.np, a, row, xl, gout - weight<D, T>(a) * c.phi,
+                                           c.phi, T(1));
         } else {
             gsum += gout;
             __builtin_nontemporal_store(typename P::G::raw(gout),
                 lane_ptr(static_cast<typename P::G::raw *>(p.Gout), (long long)a * g.np + row, xl));
         }
+    };
+#pragma unroll
+    for (int a = Q / 2 + 1; a < Q; ++a) {
+        const int b = opposite<D>(a);
+        const T w = weight<D, T>(a);
+        const T va = pull<D, typename P::G, T>(nb, p.Gin, g.np, a, p.gp_in, nullptr);
+        const T vb = pull<D, typename P::G, T>(nb, p.Gin, g.np, b, p.gp_in, nullptr);
+        const T cu = cdot<D>(a, c.ux, c.uy, c.uz);
+        T ga, gb;
+        gamma_pair(w, gbase, cu, ga, gb);
+        const T s = w * cdot<D>(a, nx, ny, nz) * src;
+        gemit(a, va + (c.phi * ga - va) * ph.inv_tpb + s);
+        gemit(b, vb + (c.phi * gb - vb) * ph.inv_tpb - s);
     }
-    if constexpr (!P::G::shifted)
+    if constexpr (P::G::shifted) {
+        constexpr int a0 = Q / 2;
+        const T v0 = pull<D, typename P::G, T>(nb, p.Gin, g.np, a0, p.gp_in, nullptr);
+        gemit(a0, v0 + (c.phi * weight<D, T>(a0) * gbase - v0) * ph.inv_tpb);
+    } else {
         __builtin_nontemporal_store(typename P::G::raw(c.phi - gsum),
             lane_ptr(static_cast<typename P::G::raw *>(p.Gout), (long long)(Q / 2) * g.np + row, xl));
+    }
     if constexpr (P::G::shifted) *lane_ptr(p.gp_out, row, xl) = float(c.phi);
 }
 
