@@ -27,40 +27,48 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # algorithmic bytes per cell for one launch of each kernel, FP32, D3Q27:
 #   collide: read 27 f' + 27 g + phi, write 27 f' + 27 g  -> 4 * (27 * 4 + 1) = 436
 #   phi:     read 27 g, write phi                          -> 4 * (27 + 1)     = 112
-ALG_BYTES = {("fp32", 3): {"collide": 436, "phi": 112, "method": 440},
-             ("fp64", 3): {"collide": 872, "phi": 224, "method": 880},
+ALG_BYTES = {("fp32", 3): {"collide": 436, "phi": 112, "method": 440, "fused": 432},
+             ("fp64", 3): {"collide": 872, "phi": 224, "method": 880, "fused": 864},
              # FP16-shifted flow set: 27 x 2 B each way, plus the per-cell shift
              # and scale (2 x 4 B) read at the source cells and written back
              ("fp16s", 3): {"collide": 2 * 27 * 2 + 2 * 27 * 4 + 4 + 2 * 8, "phi": 27 * 4 + 4,
-                            "method": 2 * 27 * 2 + 2 * 27 * 4 + 8 + 2 * 8},
+                            "method": 2 * 27 * 2 + 2 * 27 * 4 + 8 + 2 * 8,
+                            "fused": 2 * 27 * 2 + 2 * 27 * 4 + 2 * 8},
              # both sets FP16-shifted; the phase-field shift (phi, 4 B) too
              ("fp16s_all", 3): {"collide": 4 * 27 * 2 + 4 + 2 * 8 + 2 * 4, "phi": 27 * 2 + 4 + 4,
-                                "method": 4 * 27 * 2 + 8 + 2 * 8 + 2 * 4},
+                                "method": 4 * 27 * 2 + 8 + 2 * 8 + 2 * 4,
+                                "fused": 4 * 27 * 2 + 2 * 8 + 2 * 4},
              ("fp32", 2): {"collide": 4 * (2 * 2 * 9 + 1), "phi": 4 * (9 + 1), "method": 152},
              ("fp64", 2): {"collide": 8 * (2 * 2 * 9 + 1), "phi": 8 * (9 + 1), "method": 304}}
+# The one-launch step keeps phi on chip: its bytes are the populations' alone
+# (read and written once), which is also what the method must move per step.
 
 
 KERNEL_SOURCES = ("kernels.hip", "lattice.hpp", "internal.h")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_collide_k_phi_rti3d_128x128x512_fp32_hbm_bytes.md")
+TRAFFIC_PROFILES = {
+    "k_fused": os.path.join(ROOT, "profiles", "k_fused_rti3d_128x128x512_fp32_hbm_bytes.md"),
+    "k_collide": os.path.join(ROOT, "profiles", "k_collide_k_phi_rti3d_128x128x512_fp32_hbm_bytes.md"),
+}
 
 
-def profiled_traffic(storage, nz):
-    """HBM bytes per k_collide launch from the committed rocprofv3 FETCH_SIZE /
+def profiled_traffic(storage, nz, kernel="k_collide"):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (each counter scaled by its reading for a plain copy of
-    known size).  None unless that summary was taken on this workload and on
-    kernel sources identical to the ones in the tree."""
+    known size).  None unless that summary was taken on this workload, for this
+    kernel and on kernel sources identical to the ones in the tree."""
     import hashlib
 
-    if storage != "fp32" or nz != 512 or not os.path.exists(TRAFFIC_PROFILE):
+    path = TRAFFIC_PROFILES.get(kernel)
+    if storage != "fp32" or nz != 512 or path is None or not os.path.exists(path):
         return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2101_06769_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    text = open(TRAFFIC_PROFILE).read()
+    text = open(path).read()
     blob = text.split("```json", 1)[1].split("```", 1)[0]
     rec = json.loads(blob)
-    if rec["sources_sha256"] != h.hexdigest():
+    if rec["sources_sha256"] != h.hexdigest() or rec["kernel"] != kernel:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -200,7 +208,8 @@ def bench_splash(args):
         red, rc = s.reduce()
         rec = {"mlups": round(N * args.splash_steps / (ms / 1e3) / 1e6, 1),
                "ms_per_step": round(ms / args.splash_steps, 4),
-               "alg_GBs": round(ALG_BYTES[(storage.split("_floor")[0], 3)]["method"] * N *
+               "alg_GBs": round(ALG_BYTES[(storage.split("_floor")[0], 3)][
+                                    "fused" if s.uses_fused() else "method"] * N *
                                 args.splash_steps /
                                 (ms / 1e3) / 1e9, 1),
                "status": "ok" if rc == mplb.OK else "unstable",
@@ -245,7 +254,8 @@ def bench_serve(args):
     serve.serve_fifo(warm, realtime=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res_b, st = serve.serve_batched(specs, hbm_budget=int(args.hbm_budget_gb * (1 << 30)))
+    res_b, st = serve.serve_batched(specs, hbm_budget=int(args.hbm_budget_gb * (1 << 30)),
+                                    capacity=args.capacity)
     wall_b = time.perf_counter() - t0
     t0 = time.perf_counter()
     res_f = serve.serve_fifo(specs)
@@ -278,6 +288,9 @@ def main():
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16s", "fp16s_all"])
     ap.add_argument("--nz", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fuse", type=int, default=1, choices=[0, 1, 2],
+                    help="one-launch step: 0 never (phi pass + update), 1 where it is the "
+                         "faster form (default), 2 wherever it applies")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="rti3d", choices=["rti3d", "batch", "serve", "splash"],
                     help="rti3d: the 128x128x512 step (default); batch: 64 uneven domains, "
@@ -289,6 +302,7 @@ def main():
     ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0)
+    ap.add_argument("--capacity", type=int, default=256, help="serving: batch slots")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, time a plain device-to-device copy of this "
                          "many MiB (reference kernel for the HBM byte counters)")
@@ -328,6 +342,7 @@ def main():
     case = inputs.rti3d(nz=args.nz)
     N = case.ncells
     s = mplb.Solver(case.params, storage=args.storage)
+    s.set_fused(args.fuse)
     s.init(case.phi, case.u, case.p)
     s.step(args.warmup)
     torch.cuda.synchronize()
@@ -345,8 +360,12 @@ def main():
     red, rc = s.reduce()
     m0 = float(case.phi.sum())
     ab = ALG_BYTES[(args.storage, 3)]
+    fused = s.uses_fused()
+    kernel = "k_fused" if fused else "k_collide"
+    kbytes = ab["fused"] if fused else ab["collide"]
+    method_bytes = ab["fused"] if fused else ab["method"]
     t_col = ms_col / args.steps / 1e3
-    achieved = ab["collide"] * N / t_col / 1e9
+    achieved = kbytes * N / t_col / 1e9
     line = {
         "metric": "MLUPS (flow+phase field) and % HBM roofline at fixed error vs FP64",
         "value": round(mlups, 1),
@@ -367,11 +386,12 @@ def main():
                    "cells": N, "lattice": "D3Q27+D3Q27", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(args.storage, args.nz),
-                     "kernel": "k_collide", "alg_bytes_per_cell": ab["collide"],
+                     "traffic": profiled_traffic(args.storage, args.nz, kernel),
+                     "kernel": kernel, "alg_bytes_per_cell": kbytes,
                      "avg_launch_us": round(t_col * 1e6, 2),
-                     "phi_pass_avg_launch_us": round(ms_phi / args.steps * 1e3, 2)},
-        "method_alg_GBs": round(ab["method"] * N * args.steps / (ms / 1e3) / 1e9, 1),
+                     "phi_pass_avg_launch_us": None if fused else round(ms_phi / args.steps * 1e3, 2)},
+        "method_alg_GBs": round(method_bytes * N * args.steps / (ms / 1e3) / 1e9, 1),
+        "method_frac": round(method_bytes * N * args.steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "phase_mass_rel_drift": abs(red[0] - m0) / m0,
         "status": "ok" if rc == mplb.OK else "unstable",
     }

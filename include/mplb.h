@@ -174,9 +174,24 @@ int mplb_get_populations(mplb_solver *s, int32_t which, double *host_out);
  * Synchronises the stream. */
 int mplb_set_populations(mplb_solver *s, int32_t which, const double *host_in);
 
-/* Threads per block used for the step kernels (x, y, z); 0 = library default.
- * The product must be a multiple of 64 and at most 1024. */
+/* Threads per block of the two-kernel step (x, y, z); (0, 0, 0) = library
+ * default (as wide in x as the lattice, up to 256).  Between 1 and 256
+ * threads; bz = 1 in 2-D.  Blocks a multiple of 64 wide in x on lattices
+ * periodic in x take wavefront-uniform (row-form) addressing; results do not
+ * depend on the shape.  Errors: EINVAL. */
 int mplb_set_block(mplb_solver *s, int32_t bx, int32_t by, int32_t bz);
+
+/* One-launch step: for 3-D cumulant lattices periodic in x with at most 256
+ * cells per row, a step can be a single kernel that computes phi into
+ * on-chip memory and updates the cells from it, instead of a phi pass plus
+ * the update (same arithmetic, same results).  mode 0: never; 1 (default):
+ * where it is the faster form (the FP16 storage formats); 2: wherever it
+ * applies.  Errors: EINVAL (mode not 0, 1 or 2). */
+int mplb_set_fused(mplb_solver *s, int32_t mode);
+
+/* 1 if the next step of this solver runs as one launch, 0 if not; <0 on
+ * error. */
+int mplb_uses_fused(const mplb_solver *s);
 
 /* Autotuner: time candidate block shapes for the step kernels (each over
  * `steps` steps after two warm-up steps, device time from HIP events), select
@@ -216,6 +231,17 @@ int mplb_batch_set_block(mplb_batch *b, int32_t bx, int32_t by, int32_t bz);
 
 /* Graph chunk in steps (>= 1), or 0 to launch every step directly. */
 int mplb_batch_set_graph_chunk(mplb_batch *b, int32_t chunk);
+
+/* One-launch batched step, modes as mplb_set_fused (default 1): when chosen
+ * and every attached domain allows it, each batch step is one kernel over
+ * tiles of whole rows; otherwise the phi pass and the update over block
+ * tiles.  Same arithmetic, same results.  Rebuilds the tile list.  Errors:
+ * EINVAL, ENOMEM (tile list full). */
+int mplb_batch_set_fused(mplb_batch *b, int32_t mode);
+
+/* 1 if the batch currently steps with the one-launch kernel, 0 if not, <0
+ * on error. */
+int mplb_batch_uses_fused(const mplb_batch *b);
 
 /* Autotuner: time `steps` batch steps (after one warm-up step) for each
  * candidate block shape (candidates = ncand triples bx, by, bz; NULL = a

@@ -173,10 +173,15 @@ struct mplb_solver {
     int64_t steps;
     bool ready;
     bool attached;
+    int fuse;  // one-launch step: 0 never, 1 where faster (FP16 formats), 2 where it applies
     dim3 block;
     mplb::PhysD ph;
 
     void *at(size_t off) const { return off ? base + off : nullptr; }
+    bool use_fused(const mplb::Ctx &c) const
+    {
+        return fuse != 0 && mplb::fused_ok(c) && (fuse == 2 || mplb::fused_preferred(prm.storage));
+    }
     void *F(int k) const { return base + L.F[k]; }
     void *G(int k) const { return base + L.G[k]; }
     double *staging(int k) const { return reinterpret_cast<double *>(base + L.F[k]); }
@@ -262,6 +267,7 @@ int mplb_create(const mplb_params *p, void *dev_arena, size_t arena_bytes, void 
     s->ready = false;
     s->attached = false;
     s->block = default_block(p);
+    s->fuse = 1;
     s->ph = make_phys(p);
     *out = s;
     return MPLB_OK;
@@ -312,6 +318,20 @@ int mplb_tune_block(mplb_solver *s, int32_t steps, const int32_t *candidates, in
     return MPLB_OK;
 }
 
+int mplb_set_fused(mplb_solver *s, int32_t mode)
+{
+    if (!s) return fail(MPLB_EINVAL, "solver is NULL");
+    if (mode < 0 || mode > 2) return fail(MPLB_EINVAL, "mode must be 0, 1 or 2");
+    s->fuse = mode;
+    return MPLB_OK;
+}
+
+int mplb_uses_fused(const mplb_solver *s)
+{
+    if (!s) return fail(MPLB_EINVAL, "solver is NULL");
+    return s->use_fused(s->ctx(s->cur)) ? 1 : 0;
+}
+
 int mplb_set_block(mplb_solver *s, int32_t bx, int32_t by, int32_t bz)
 {
     if (!s) return fail(MPLB_EINVAL, "solver is NULL");
@@ -358,8 +378,12 @@ int mplb_step(mplb_solver *s, int64_t nsteps)
     if (s->attached) return fail(MPLB_ESTATE, "solver is attached to a batch");
     for (int64_t i = 0; i < nsteps; ++i) {
         const mplb::Ctx c = s->ctx(s->cur);
-        HIPCHK(mplb::launch_phi(c));
-        HIPCHK(mplb::launch_collide(c));
+        if (s->use_fused(c)) {
+            HIPCHK(mplb::launch_step_fused(c));
+        } else {
+            HIPCHK(mplb::launch_phi(c));
+            HIPCHK(mplb::launch_collide(c));
+        }
         s->cur ^= 1;
         s->steps++;
     }
@@ -381,9 +405,10 @@ int mplb_step_timed(mplb_solver *s, int64_t nsteps, double *ms_phi, double *ms_c
         hipError_t e = hipEventRecord(ev[0], s->stream);
         for (int i = 0; i < k && e == hipSuccess; ++i) {
             const mplb::Ctx c = s->ctx(s->cur);
-            e = mplb::launch_phi(c);
+            const bool fused = s->use_fused(c);
+            e = fused ? hipSuccess : mplb::launch_phi(c);
             if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 1], s->stream);
-            if (e == hipSuccess) e = mplb::launch_collide(c);
+            if (e == hipSuccess) e = fused ? mplb::launch_step_fused(c) : mplb::launch_collide(c);
             if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 2], s->stream);
             s->cur ^= 1;
             s->steps++;
@@ -510,10 +535,12 @@ struct mplb_batch {
     std::vector<mplb::BatchDom> doms;
     std::vector<mplb::BatchTile> tiles;
     int ntiles_host;
+    int grid;     // blocks per launch: tile count rounded up to a bucket (0 = persistent)
     dim3 block;
-    int grid;
     int chunk;
     bool row;     // row-form kernels (see row_form_ok)
+    int fuse;     // one-launch step: 0 never, 1 where faster (FP16 formats), 2 where allowed
+    bool fused;   // one-launch step over fused tiles
     long long t;  // batch steps taken
     hipGraphExec_t exec;
     bool have_graph;
@@ -547,19 +574,48 @@ void drop_graph(mplb_batch *b)
 int upload_tables(mplb_batch *b)
 {
     b->tiles.clear();
+    bool fused = b->fuse == 2 || (b->fuse == 1 && mplb::fused_preferred(b->storage));
+    for (int i = 0; i < b->capacity; ++i)
+        if (b->slot[i])
+            fused = fused && mplb::fused_ok_geom(b->dim, b->collision, b->doms[i].g);
     const int bx = b->block.x, by = b->block.y, bz = b->block.z;
     for (int i = 0; i < b->capacity; ++i) {
         const mplb_solver *s = b->slot[i];
         if (!s) continue;
-        for (int z0 = 0; z0 < s->prm.n[2]; z0 += bz)
-            for (int y0 = 0; y0 < s->prm.n[1]; y0 += by)
-                for (int x0 = 0; x0 < s->prm.n[0]; x0 += bx) {
+        const int nx = s->prm.n[0], ny = s->prm.n[1], nz = s->prm.n[2];
+        if (fused) {
+            // whole rows, chunks of 32 planes
+            const int rows = mplb::fused_rows(nx), zc = 32;
+            for (int y0 = 0; y0 < ny; y0 += rows)
+                for (int z0 = 0; z0 < nz; z0 += zc) {
                     if ((long long)b->tiles.size() >= b->max_tiles)
                         return fail(MPLB_ENOMEM, "batch tile list is full");
-                    b->tiles.push_back(mplb::BatchTile{i, x0, y0, z0});
+                    b->tiles.push_back(mplb::BatchTile{i, 0, y0, z0, z0 + zc < nz ? z0 + zc : nz});
+                }
+            continue;
+        }
+        // block tiles (one block depth in z)
+        const int zt = bz;
+        for (int z0 = 0; z0 < nz; z0 += zt)
+            for (int y0 = 0; y0 < ny; y0 += by)
+                for (int x0 = 0; x0 < nx; x0 += bx) {
+                    if ((long long)b->tiles.size() >= b->max_tiles)
+                        return fail(MPLB_ENOMEM, "batch tile list is full");
+                    b->tiles.push_back(mplb::BatchTile{i, x0, y0, z0, z0 + zt < nz ? z0 + zt : nz});
                 }
     }
+    if (fused != b->fused) drop_graph(b);
+    b->fused = fused;
     b->ntiles_host = int(b->tiles.size());
+    {
+        // one block per tile, hardware-scheduled; the launch size moves in
+        // buckets of 4096 blocks so that a captured graph survives most
+        // attach / detach events (surplus blocks find no tile and exit)
+        const int bucket = 4096;
+        const int grid = b->ntiles_host ? (b->ntiles_host + bucket - 1) / bucket * bucket : bucket;
+        if (grid != b->grid) drop_graph(b);
+        b->grid = grid;
+    }
     bool row = true;
     for (int i = 0; i < b->capacity; ++i)
         if (b->slot[i]) row = row && mplb::row_form_ok(b->dim, b->doms[i].g, b->block);
@@ -621,12 +677,14 @@ int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t ma
     b->slot.assign(capacity, nullptr);
     b->doms.assign(capacity, mplb::BatchDom{});
     b->ntiles_host = 0;
+    b->grid = 0;
     b->block = dim3(64, 4, 1);
-    b->grid = 2048;
     b->chunk = 16;
     b->t = 0;
     b->have_graph = false;
     b->row = true;
+    b->fuse = 1;
+    b->fused = false;
     const int rc = upload_tables(b);
     if (rc != MPLB_OK) {
         delete b;
@@ -645,6 +703,20 @@ int mplb_batch_set_block(mplb_batch *b, int32_t bx, int32_t by, int32_t bz)
     b->block = dim3(bx, by, bz);
     drop_graph(b);
     return upload_tables(b);
+}
+
+int mplb_batch_set_fused(mplb_batch *b, int32_t mode)
+{
+    if (!b) return fail(MPLB_EINVAL, "batch is NULL");
+    if (mode < 0 || mode > 2) return fail(MPLB_EINVAL, "mode must be 0, 1 or 2");
+    b->fuse = mode;
+    return upload_tables(b);
+}
+
+int mplb_batch_uses_fused(const mplb_batch *b)
+{
+    if (!b) return fail(MPLB_EINVAL, "batch is NULL");
+    return b->fused ? 1 : 0;
 }
 
 int mplb_batch_set_graph_chunk(mplb_batch *b, int32_t chunk)
@@ -742,13 +814,18 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
         HIPCHK(mplb::launch_set_i64(b->d_tbase, b->t, b->stream));
         if (b->chunk > 0 && left >= b->chunk) {
             if (!b->have_graph) {
+                // persistent grid sizes are looked up outside the capture
+                HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row,
+                                               b->fused, b->d_doms, b->d_tiles, b->d_ntiles,
+                                               b->d_tbase, 0, b->block, b->stream, true));
                 hipGraph_t graph = nullptr;
                 HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
                 hipError_t e = hipSuccess;
                 for (int k = 0; k < b->chunk && e == hipSuccess; ++k)
-                    e = mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row, b->d_doms,
-                                                b->d_tiles, b->d_ntiles, b->d_tbase, k, b->block, b->grid,
-                                                b->stream);
+                    e = mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row,
+                                                b->fused, b->d_doms, b->d_tiles, b->d_ntiles,
+                                                b->d_tbase, k, b->block, b->stream, false,
+                                                b->grid);
                 // always end the capture, so that a failure leaves the stream usable
                 const hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
                 if (e != hipSuccess || e2 != hipSuccess) {
@@ -766,8 +843,9 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
             b->t += b->chunk;
             done += b->chunk;
         } else {
-            HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row, b->d_doms, b->d_tiles, b->d_ntiles,
-                                           b->d_tbase, 0, b->block, b->grid, b->stream));
+            HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row, b->fused,
+                                           b->d_doms, b->d_tiles, b->d_ntiles, b->d_tbase, 0,
+                                           b->block, b->stream, false, b->grid));
             b->t += 1;
             done += 1;
         }

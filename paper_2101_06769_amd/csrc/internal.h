@@ -53,6 +53,17 @@ struct Ctx {
 
 hipError_t launch_phi(const Ctx &c);
 hipError_t launch_collide(const Ctx &c);
+// One-launch step (phi into LDS, then the collision) for 3-D cumulant
+// lattices periodic in x with nx <= 256 and arrays of fewer than 2^31
+// elements; fused_ok tells whether it applies.  It does not write the phi
+// array (launch_phi refreshes it for readers).
+bool fused_ok(const Ctx &c);
+bool fused_ok_geom(int dim, int collision, const Geom &g);
+// Storage formats for which the fused step is the faster one.
+bool fused_preferred(int storage);
+// Rows per tile of the fused kernel for rows of nx cells (512 threads).
+int fused_rows(int nx);
+hipError_t launch_step_fused(const Ctx &c);
 // Equilibrium initial state from device FP64 fields (phi[N], u[dim][N], p[N])
 // written into the Fout/Gout buffers in pull layout.
 hipError_t launch_init(const Ctx &c, const double *phi, const double *u, const double *pr);
@@ -80,9 +91,11 @@ struct BatchDom {
     long long first, last;  // active for batch steps first <= t < last
 };
 
-// A tile of a batch: domain index and the tile's origin cell.
+// A tile of a batch: domain index, origin cell (x0, y0, z0) and the end of
+// its plane range z1: a block-shaped tile repeated along z up to z1, or, for
+// the fused kernels, whole rows y0 .. y0 + rows - 1 over planes z0 .. z1 - 1.
 struct BatchTile {
-    int dom, x0, y0, z0;
+    int dom, x0, y0, z0, z1;
 };
 
 // One step of every active domain: persistent blocks stride over the tile
@@ -91,9 +104,16 @@ struct BatchTile {
 // x periodic, population arrays of fewer than 2^31 elements.
 bool row_form_ok(int dim, const Geom &g, dim3 block);
 // row: every attached domain satisfies row_form_ok with this block.
-hipError_t launch_batch_step(int dim, int storage, int collision, bool row, const BatchDom *doms,
-                             const BatchTile *tiles, const int *ntiles, const long long *tbase,
-                             int step_off, dim3 block, int grid, hipStream_t stream);
+// fused: one kernel per step over fused tiles (every attached domain
+// satisfies fused_ok_geom); else the phi pass and the update over block
+// tiles.  The blocks stride over the tile list: fixed_grid > 0 launches that
+// many blocks (at least one per tile: hardware scheduling), else a persistent
+// grid sized to the device; prepare_only looks the persistent sizes up
+// without launching (call it before a graph capture).
+hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool fused,
+                             const BatchDom *doms, const BatchTile *tiles, const int *ntiles,
+                             const long long *tbase, int step_off, dim3 block,
+                             hipStream_t stream, bool prepare_only = false, int fixed_grid = 0);
 hipError_t launch_set_i64(long long *ptr, long long v, hipStream_t stream);
 
 }  // namespace mplb

@@ -30,6 +30,9 @@
 #include <hip/hip_fp16.h>
 
 #include <type_traits>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 #include "internal.h"
 
@@ -703,6 +706,116 @@ k_collide(Geom g, Phys<typename P::T> ph, Ptrs p)
     collide_cell<D, P, COLL, NbOf<ROW>>(g, ph, p, x, y, z);
 }
 
+// ------------------------------------------------------------- fused step
+// One launch per time step for 3-D lattices periodic in x with at most 256
+// cells per row.  A block of 512 threads covers bx-wide rows (bx = 64, 128 or
+// 256 >= nx, so a row and its periodic x-neighbours are all in the block) for
+// by = 512 / bx rows and marches along z over a chunk of planes.  For each
+// plane it first sums the pulled g into the order parameter of its rows and
+// one halo row on either side (Sec. 2.2, zeroth moment), into a ring of three
+// LDS planes, then updates the middle plane with the stencil read from LDS.
+// The pulled g of a cell are read twice (for phi, then for the collision) but
+// the second read finds them in cache, and phi never goes to HBM.
+
+constexpr int FUSED_THREADS = 512;
+constexpr int FUSED_LDS = 3 * FUSED_THREADS * 2;  // three planes of (by + 2) bx <= 1024 cells
+
+__host__ __device__ constexpr int fused_bx(int nx) { return nx <= 64 ? 64 : nx <= 128 ? 128 : 256; }
+
+// Neighbourhood of a cell of the fused kernel: row-form pulls, stencil from
+// the LDS rows of planes z - 1, z, z + 1 (each row `rowlen` long, the cell's
+// own row in the middle of three).
+template <typename T>
+struct NbFused : NbRow {
+    const T *pl[3];
+    int rowlen;
+};
+
+template <typename T>
+__device__ __forceinline__ T phi_at(const NbFused<T> &n, const T *, int cx, int cy, int cz)
+{
+    const int xx = cx == 0 ? n.x : cx > 0 ? n.xp : n.xm;
+    return n.pl[1 + cz][cy * n.rowlen + xx];
+}
+
+// Coordinate s on an axis of n cells for the halo rows and planes of the
+// fused kernel: wrapped on a periodic axis (any s), else clamped (the ghost
+// layer mirrors the first fluid layer; beyond a partial tile the value is
+// computed but not used).
+__device__ __forceinline__ int halo_coord(int s, int n, int bc)
+{
+    if (bc == BC_PER) return ((s % n) + n) % n;
+    return s < 0 ? 0 : s >= n ? n - 1 : s;
+}
+
+// Planes z0 <= z < z1 of rows y0 .. y0 + by - 1 (whole rows), by one block
+// of FUSED_THREADS threads; sphi is the block's LDS.  Every thread of the
+// block must call it; it ends with a barrier, so sphi may be reused after.
+template <int D, class P, int COLL>
+__device__ __forceinline__ void fused_tile(const Geom &g, const Phys<typename P::T> &ph,
+                                           const Ptrs &p, int y0, int z0, int z1,
+                                           typename P::T *sphi)
+{
+    using T = typename P::T;
+    constexpr int Q = Lat<D>::Q;
+    const int bx = fused_bx(g.nx), by = FUSED_THREADS / bx;
+    const int tid = int(threadIdx.x);
+    const int x = tid & (bx - 1);
+    const int ty = __builtin_amdgcn_readfirstlane(tid / bx);  // one row per wavefront
+    const int psz = (by + 2) * bx;
+    const bool xin = x < g.nx;
+    // phi of plane zz (halo-mapped) for rows y0 - 1 .. y0 + by into LDS slot
+    auto plane = [&](int zz, int slot) {
+        const int zh = halo_coord(zz, g.nz, g.bcz);
+        for (int r = ty; r < by + 2; r += by) {
+            const int yh = halo_coord(y0 - 1 + r, g.ny, g.bcy);
+            if (xin) {
+                const NbRow nb = make_nb(g, x, yh, zh, (NbRow *)nullptr);
+                T sum = 0;
+#pragma unroll
+                for (int a = 0; a < Q; ++a)
+                    sum += pull<D, typename P::G, T>(nb, p.Gin, g.np, a, p.gp_in, nullptr);
+                sphi[slot * psz + r * bx + x] = sum;
+            }
+        }
+    };
+    int sm = 0, s0 = 1, sp = 2;  // LDS slots of planes z - 1, z, z + 1
+    plane(z0 - 1, sm);
+    plane(z0, s0);
+    for (int z = z0; z < z1; ++z) {
+        plane(z + 1, sp);
+        __syncthreads();
+        const int y = y0 + ty;
+        if (xin && y < g.ny) {
+            NbFused<T> n;
+            static_cast<NbRow &>(n) = make_nb(g, x, y, z, (NbRow *)nullptr);
+            n.pl[0] = sphi + sm * psz + (ty + 1) * bx;
+            n.pl[1] = sphi + s0 * psz + (ty + 1) * bx;
+            n.pl[2] = sphi + sp * psz + (ty + 1) * bx;
+            n.rowlen = bx;
+            collide_body<D, P, COLL>(n, g, ph, p);
+        }
+        __syncthreads();  // the slot of plane z - 1 is overwritten next
+        const int t = sm;
+        sm = s0;
+        s0 = sp;
+        sp = t;
+    }
+}
+
+template <int D, class P, int COLL>
+__global__ void __launch_bounds__(FUSED_THREADS)
+__attribute__((amdgpu_waves_per_eu(collide_waves<D, P, COLL>())))
+k_fused(Geom g, Phys<typename P::T> ph, Ptrs p, int zc)
+{
+    using T = typename P::T;
+    __shared__ T sphi[FUSED_LDS];
+    const int by = FUSED_THREADS / fused_bx(g.nx);
+    const int z0 = int(blockIdx.z) * zc;
+    fused_tile<D, P, COLL>(g, ph, p, int(blockIdx.y) * by, z0, z0 + zc < g.nz ? z0 + zc : g.nz,
+                           sphi);
+}
+
 // Equilibrium initial state, computed in FP64 for every storage format and
 // scattered to the slots the first step pulls from.
 template <int D, class P>
@@ -970,16 +1083,44 @@ __attribute__((amdgpu_waves_per_eu(PHI ? 1 : collide_waves<D, P, COLL>()))) kb_s
     const int nt = *ntiles;
     for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
         const BatchTile tl = tiles[ti];
-        const BatchDom &d = doms[tl.dom];
-        if (t < d.first || t >= d.last) continue;
+        // the domain's record by value: read once, not re-read after every
+        // population store the compiler cannot prove to be elsewhere
+        const Geom g = doms[tl.dom].g;
+        const long long first = doms[tl.dom].first, last = doms[tl.dom].last;
+        if (t < first || t >= last) continue;
+        const Ptrs p = batch_ptrs(doms[tl.dom], int((t - first) & 1));
         int x, y, z;
         thread_cell<ROW>(tl.x0, tl.y0, tl.z0, x, y, z);
-        if (x >= d.g.nx || y >= d.g.ny || z >= d.g.nz) continue;
-        const Ptrs p = batch_ptrs(d, int((t - d.first) & 1));
-        if constexpr (PHI)
-            phi_cell<D, P, NbOf<ROW>>(d.g, p, x, y, z);
-        else
-            collide_cell<D, P, COLL, NbOf<ROW>>(d.g, to_phys<T>(d.ph), p, x, y, z);
+        if (x >= g.nx || y >= g.ny || z >= tl.z1) continue;
+        if constexpr (PHI) {
+            phi_cell<D, P, NbOf<ROW>>(g, p, x, y, z);
+        } else {
+            const Phys<T> ph = to_phys<T>(doms[tl.dom].ph);
+            collide_cell<D, P, COLL, NbOf<ROW>>(g, ph, p, x, y, z);
+        }
+    }
+}
+
+// Batched one-launch step: persistent blocks stride over fused tiles (domain,
+// rows y0 .., planes z0 .. z1 - 1), each a fused_tile of its domain.
+template <int D, class P, int COLL>
+__global__ void __launch_bounds__(FUSED_THREADS)
+__attribute__((amdgpu_waves_per_eu(collide_waves<D, P, COLL>())))
+kb_fused(const BatchDom *__restrict__ doms, const BatchTile *__restrict__ tiles, const int *ntiles,
+         const long long *tbase, int step_off)
+{
+    using T = typename P::T;
+    __shared__ T sphi[FUSED_LDS];
+    const long long t = *tbase + step_off;
+    const int nt = *ntiles;
+    for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
+        const BatchTile tl = tiles[ti];
+        const Geom g = doms[tl.dom].g;  // by value, see kb_step
+        const long long first = doms[tl.dom].first, last = doms[tl.dom].last;
+        if (t < first || t >= last) continue;
+        const Ptrs p = batch_ptrs(doms[tl.dom], int((t - first) & 1));
+        const Phys<T> ph = to_phys<T>(doms[tl.dom].ph);
+        fused_tile<D, P, COLL>(g, ph, p, tl.y0, tl.z0, tl.z1, sphi);
     }
 }
 
@@ -1057,6 +1198,67 @@ hipError_t launch_collide(const Ctx &c)
     });
 }
 
+bool fused_ok_geom(int dim, int collision, const Geom &g)
+{
+    const long long Q = 27;
+    return dim == 3 && collision == 0 && g.bcx == BC_PER && g.nx <= 256 && Q * g.np < (1ll << 31);
+}
+
+bool fused_ok(const Ctx &c) { return fused_ok_geom(c.dim, c.ph.collision, c.g); }
+
+// The fused step re-reads each cell's g (and the halo rows') after the phi
+// sum; at FP32 and FP64 the per-XCD L2 does not hold a tile's planes that
+// long and the re-reads cost more than the phi pass they replace (measured
+// 974 vs 846 us at 128x128x512 FP32).  With FP16 populations it wins.
+bool fused_preferred(int storage) { return storage == ST_FP16S || storage == ST_FP16S_ALL; }
+
+int fused_rows(int nx) { return FUSED_THREADS / fused_bx(nx); }
+
+// Planes per block: about 1024 blocks (measured faster than 512, which fill
+// the device once with long sequential marches), at least 8 planes so that
+// the two prologue planes stay cheap.
+static int fused_zc(const Ctx &c, int by)
+{
+    const int tiles_y = (c.g.ny + by - 1) / by;
+    int chunks = 1024 / tiles_y;
+    if (chunks < 1) chunks = 1;
+    int zc = (c.g.nz + chunks - 1) / chunks;
+    if (zc < 8) zc = 8;
+    return zc;
+}
+
+hipError_t launch_step_fused(const Ctx &c)
+{
+    const int by = fused_rows(c.g.nx);
+    const int zc = fused_zc(c, by);
+    const dim3 grid(1, (c.g.ny + by - 1) / by, (c.g.nz + zc - 1) / zc);
+    return dispatch(c, [&]<int D, class P>() {
+        if constexpr (D != 3) {
+            return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((k_fused<3, P, 0>), grid, dim3(FUSED_THREADS), 0, c.stream, c.g,
+                               to_phys<typename P::T>(c.ph), c.p, zc);
+            return hipGetLastError();
+        }
+    });
+}
+
+// Blocks of `kernel` resident on the whole device at once: the size of a
+// persistent grid (larger grids would start their surplus blocks only after
+// the first ones have walked their whole share of the tile list).
+template <class K>
+static int resident_blocks(K kernel, int threads)
+{
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu * prop.multiProcessorCount;
+}
+
 hipError_t launch_init(const Ctx &c, const double *phi, const double *u, const double *pr)
 {
     return dispatch(c, [&]<int D, class P>() {
@@ -1104,35 +1306,48 @@ hipError_t launch_field(const Ctx &c, int field, double *dst)
     });
 }
 
-hipError_t launch_batch_step(int dim, int storage, int collision, bool row, const BatchDom *doms,
-                             const BatchTile *tiles, const int *ntiles, const long long *tbase,
-                             int step_off, dim3 block, int grid, hipStream_t stream)
+hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool fused,
+                             const BatchDom *doms, const BatchTile *tiles, const int *ntiles,
+                             const long long *tbase, int step_off, dim3 block,
+                             hipStream_t stream, bool prepare_only, int fixed_grid)
 {
     Ctx c{};
     c.dim = dim;
     c.storage = storage;
-    return dispatch(c, [&]<int D, class P>() {
-        if (row)
-            hipLaunchKernelGGL((kb_step<D, P, 0, true, true>), dim3(grid), block, 0, stream, doms,
-                               tiles, ntiles, tbase, step_off);
-        else
-            hipLaunchKernelGGL((kb_step<D, P, 0, true, false>), dim3(grid), block, 0, stream, doms,
-                               tiles, ntiles, tbase, step_off);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        if (collision == 0 && row)
-            hipLaunchKernelGGL((kb_step<D, P, 0, false, true>), dim3(grid), block, 0, stream, doms,
-                               tiles, ntiles, tbase, step_off);
-        else if (collision == 0)
-            hipLaunchKernelGGL((kb_step<D, P, 0, false, false>), dim3(grid), block, 0, stream,
-                               doms, tiles, ntiles, tbase, step_off);
-        else if (row)
-            hipLaunchKernelGGL((kb_step<D, P, 1, false, true>), dim3(grid), block, 0, stream, doms,
-                               tiles, ntiles, tbase, step_off);
-        else
-            hipLaunchKernelGGL((kb_step<D, P, 1, false, false>), dim3(grid), block, 0, stream,
-                               doms, tiles, ntiles, tbase, step_off);
+    const int threads = int(block.x * block.y * block.z);
+    // launches kernel k over a persistent grid sized to the device (the size
+    // is looked up once per kernel, outside any graph capture: prepare_only)
+    auto go = [&](auto k, dim3 blk, int nthreads) {
+        static std::vector<std::pair<const void *, int>> cache;
+        static std::mutex mu;
+        int grid = 0;
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            for (auto &e : cache)
+                if (e.first == reinterpret_cast<const void *>(k)) grid = e.second;
+            if (grid == 0) {
+                grid = resident_blocks(k, nthreads);
+                cache.emplace_back(reinterpret_cast<const void *>(k), grid);
+            }
+        }
+        if (prepare_only) return hipSuccess;
+        if (fixed_grid > 0) grid = fixed_grid;
+        hipLaunchKernelGGL(k, dim3(grid), blk, 0, stream, doms, tiles, ntiles, tbase, step_off);
         return hipGetLastError();
+    };
+    return dispatch(c, [&]<int D, class P>() {
+        if constexpr (D == 3) {
+            if (fused) return go(kb_fused<3, P, 0>, dim3(FUSED_THREADS), FUSED_THREADS);
+        }
+        if (fused) return hipErrorInvalidValue;
+        hipError_t e = row ? go(kb_step<D, P, 0, true, true>, block, threads)
+                           : go(kb_step<D, P, 0, true, false>, block, threads);
+        if (e != hipSuccess) return e;
+        if (collision == 0)
+            return row ? go(kb_step<D, P, 0, false, true>, block, threads)
+                       : go(kb_step<D, P, 0, false, false>, block, threads);
+        return row ? go(kb_step<D, P, 1, false, true>, block, threads)
+                   : go(kb_step<D, P, 1, false, false>, block, threads);
     });
 }
 

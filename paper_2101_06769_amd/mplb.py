@@ -83,6 +83,8 @@ def load_library():
     lib.mplb_get_populations.argtypes = [vp, ctypes.c_int32, dp]
     lib.mplb_set_populations.argtypes = [vp, ctypes.c_int32, dp]
     lib.mplb_set_block.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.mplb_set_fused.argtypes = [vp, ctypes.c_int32]
+    lib.mplb_uses_fused.argtypes = [vp]
     lib.mplb_destroy.argtypes = [vp]
     lib.mplb_destroy.restype = None
     i32p = ctypes.POINTER(ctypes.c_int32)
@@ -93,6 +95,8 @@ def load_library():
                                       ctypes.c_int64, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     lib.mplb_batch_set_block.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.mplb_batch_set_graph_chunk.argtypes = [vp, ctypes.c_int32]
+    lib.mplb_batch_set_fused.argtypes = [vp, ctypes.c_int32]
+    lib.mplb_batch_uses_fused.argtypes = [vp]
     lib.mplb_batch_tune_block.argtypes = [vp, ctypes.c_int32, i32p, ctypes.c_int32, i32p, dp]
     lib.mplb_batch_attach.argtypes = [vp, vp, ctypes.c_int64, i32p]
     lib.mplb_batch_detach.argtypes = [vp, ctypes.c_int32]
@@ -252,6 +256,16 @@ class Solver:
         assert a.size == self.Q * self.N
         check(self._lib.mplb_set_populations(self.h, int(which), _dptr(a)))
 
+    def set_fused(self, mode=2):
+        """0: two-kernel step; 1: one-launch step where faster (FP16); 2: wherever it applies."""
+        check(self._lib.mplb_set_fused(self.h, int(mode)))
+
+    def uses_fused(self):
+        r = self._lib.mplb_uses_fused(self.h)
+        if r < 0:
+            check(r)
+        return bool(r)
+
     def set_block(self, bx, by, bz=1):
         check(self._lib.mplb_set_block(self.h, int(bx), int(by), int(bz)))
 
@@ -309,6 +323,16 @@ class Batch:
 
     def set_graph_chunk(self, chunk):
         check(self._lib.mplb_batch_set_graph_chunk(self.h, int(chunk)))
+
+    def set_fused(self, mode=2):
+        """0: two-kernel step; 1: one-launch step where faster (FP16); 2: wherever it applies."""
+        check(self._lib.mplb_batch_set_fused(self.h, int(mode)))
+
+    def uses_fused(self):
+        r = self._lib.mplb_batch_uses_fused(self.h)
+        if r < 0:
+            check(r)
+        return bool(r)
 
     def tune_block(self, steps=4, candidates=None):
         """Fastest block shape for the attached domains (advances them; tune a copy)."""
