@@ -237,6 +237,104 @@ def bench_splash(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_rti2d_convergence(args):
+    """Resolution study of the 2-D Rayleigh-Taylor case (Sec. 3.2): At 0.5,
+    Re 256 and 2048, box L x 4L with L = 150, 300, 600 under acoustic scaling
+    (U* = sqrt(g L) = 0.06, so g = 0.0036 / L and nu = 0.06 L / Re), interface
+    2L + (L/10) cos(2 pi x / L), FP32.  Spike and bubble positions (in units
+    of L from the bottom wall) at t/T = 0.5 .. 5, T = L / U*."""
+    from paper_2101_06769_amd import diagnostics, inputs, mplb
+
+    out = {}
+    t0 = time.perf_counter()
+    for Re in (256.0, 2048.0):
+        for L in (150, 300, 600):
+            case = inputs.rti2d(nx=L, ny=4 * L, At=0.5, Re=Re, W=4.0, M=0.1, amp=0.1 * L)
+            T = case.meta["T"]
+            s = mplb.Solver(case.params, storage="fp32")
+            s.init(case.phi, case.u, case.p)
+            rows, done = [], 0
+            for k in range(1, 11):
+                target = int(round(0.5 * k * T))
+                s.step(target - done)
+                done = target
+                spike, bubble = diagnostics.rti_positions(s.read(0), 2)
+                rows.append([0.5 * k, None if spike is None else round(spike / L, 4),
+                             None if bubble is None else round(bubble / L, 4)])
+            red, rc = s.reduce()
+            out["Re%d_L%d" % (Re, L)] = {"t_over_T,spike/L,bubble/L": rows,
+                                          "status": "ok" if rc == mplb.OK else "unstable"}
+    wall = time.perf_counter() - t0
+    for Re in (256, 2048):
+        a = out["Re%d_L300" % Re]["t_over_T,spike/L,bubble/L"]
+        b = out["Re%d_L600" % Re]["t_over_T,spike/L,bubble/L"]
+        out["Re%d_max_spike_change_300_to_600" % Re] = max(
+            abs(x[1] - y[1]) for x, y in zip(a, b) if x[1] is not None and y[1] is not None)
+    print(json.dumps({"workload": "2-D Rayleigh-Taylor resolution study, At 0.5, Re 256/2048, "
+                                  "L = 150/300/600, to t/T = 5", "wall_s": round(wall, 1),
+                      "results": out}), flush=True)
+
+
+def bench_stability(args):
+    """Stability of the cumulant collision against single relaxation time
+    (Sec. 2.3, 4): 2-D Rayleigh-Taylor, 128 x 512, density ratios 3, 19 and
+    1000, Re 256 .. 65536 (relaxation rate omega up to 1.9999), FP32, 4000
+    steps; the step by which the state first holds a non-finite value."""
+    from paper_2101_06769_amd import inputs, mplb
+
+    table = []
+    for At in (0.5, 0.9, 0.998):
+        for Re in (256.0, 2048.0, 16384.0, 65536.0):
+            case = inputs.rti2d(nx=128, ny=512, At=At, Re=Re, W=4.0, M=0.1, amp=12.8)
+            nu = case.params["nu_h"]
+            row = {"At": At, "rho_ratio": round((1 + At) / (1 - At), 1), "Re": Re,
+                   "omega": round(1.0 / (3.0 * nu + 0.5), 6)}
+            for name, coll in (("cumulant", 0), ("srt", 1)):
+                s = mplb.Solver(case.params, storage="fp32", collision=coll)
+                s.init(case.phi, case.u, case.p)
+                blown = None
+                for k in range(20):
+                    s.step(200)
+                    red, rc = s.reduce()
+                    if rc != mplb.OK or red[4] > 0.5:
+                        blown = (k + 1) * 200
+                        break
+                row[name] = "stable" if blown is None else "diverged by step %d" % blown
+            table.append(row)
+            print(json.dumps(row), flush=True)
+    print(json.dumps({"workload": "collision stability map, 2-D Rayleigh-Taylor 128x512, 4000 steps",
+                      "rows": table}), flush=True)
+
+
+def bench_splash2d(args):
+    """2-D droplet impact on a liquid film (Sec. 3.4): D = 100, symmetry
+    planes left and right, density ratio 1000, viscosity ratio 15; the
+    paper's three cases (Re, We) = (200, 220), (1000, 220), (1000, 2200);
+    spreading radius r_K / D at t / T = 0.1 .. 1.5 beside 1.1 sqrt(t / T)."""
+    from paper_2101_06769_amd import diagnostics, inputs, mplb
+
+    out = {}
+    for Re, We in ((200.0, 220.0), (1000.0, 220.0), (1000.0, 2200.0)):
+        case = inputs.splash2d(D=100.0, Re=Re, We=We)
+        D, T = case.meta["D"], case.meta["T"]
+        s = mplb.Solver(case.params, storage="fp32")
+        s.init(case.phi, case.u, case.p)
+        rows, done = [], 0
+        for k in range(1, 16):
+            target = int(round(0.1 * k * T))
+            s.step(target - done)
+            done = target
+            r = diagnostics.spreading_radius(s.read(0), case.meta["x_axis"],
+                                             case.meta["sheet"] + 0.5 * case.params["W"])
+            rows.append([round(0.1 * k, 2), round(r / D, 4), round(1.1 * (0.1 * k) ** 0.5, 4)])
+        red, rc = s.reduce()
+        out["Re%d_We%d" % (Re, We)] = {"K": round(case.meta["K"], 1),
+                                        "t_over_T,rK/D,1.1sqrt(t/T)": rows,
+                                        "status": "ok" if rc == mplb.OK else "unstable"}
+    print(json.dumps({"workload": "2-D droplet impact on a film, D 100, 800x400, symmetry sides, W 5",
+                      "results": out}), flush=True)
+
+
 def bench_serve(args):
     """Serving: seeded Poisson arrivals (20/s) of 2-D solves (Rayleigh-Taylor,
     static drop, impacting drop; edge log-uniform 64..1024, density ratio
@@ -292,7 +390,9 @@ def main():
                     help="one-launch step: 0 never (phi pass + update), 1 where it is the "
                          "faster form (default), 2 wherever it applies")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--workload", default="rti3d", choices=["rti3d", "batch", "serve", "splash"],
+    ap.add_argument("--workload", default="rti3d",
+                    choices=["rti3d", "batch", "serve", "splash", "rti2d_convergence", "stability",
+                             "splash2d"],
                     help="rti3d: the 128x128x512 step (default); batch: 64 uneven domains, "
                          "batched vs one per launch; serve: request replay; splash: "
                          "512x512x256 droplet impact in FP64 / FP32 / FP16")
@@ -323,6 +423,12 @@ def main():
         return bench_serve(args)
     if args.workload == "splash":
         return bench_splash(args)
+    if args.workload == "rti2d_convergence":
+        return bench_rti2d_convergence(args)
+    if args.workload == "stability":
+        return bench_stability(args)
+    if args.workload == "splash2d":
+        return bench_splash2d(args)
     if args.copy_probe:
         n = args.copy_probe << 20
         a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)

@@ -88,10 +88,12 @@ def _finish(solver, keep_fields):
 
 
 def serve_batched(specs, dim=2, storage="fp32", hbm_budget=8 << 30, capacity=64, quantum=64,
-                  chunk=16, realtime=True, keep_fields=False, block=None, on_event=None):
+                  chunk=16, realtime=True, keep_fields=False, block=(128, 2, 1), on_event=None):
     """Continuous batching. Returns (results, stats). stats holds the peak
     device bytes admitted, the peak number of concurrent solves and the
-    batch steps taken."""
+    batch steps taken.  The batch advances `quantum` steps between
+    admission / completion checks (a finished solve waits at most that long
+    to be collected; a new one at most that long to join)."""
     import torch
 
     batch = mplb.Batch(dim, storage, capacity=capacity, max_tiles=1 << 22)
@@ -132,9 +134,9 @@ def serve_batched(specs, dim=2, storage="fp32", hbm_budget=8 << 30, capacity=64,
         if not active:
             rp.wait_next()
             continue
-        q = min(quantum, min(batch.remaining(sl) for sl in active))
-        if q > 0:
-            batch.step(q)
+        # a full quantum: a solve whose window closes inside it stops at its
+        # own last step (the batch skips it), and is collected after
+        batch.step(quantum)
         for sl in [sl for sl in active if batch.remaining(sl) == 0]:
             spec, s, need, t_adm, cells = active.pop(sl)
             batch.detach(sl)

@@ -88,3 +88,19 @@ def test_serving_spec_is_seeded_and_within_ranges():
         assert c.params["dim"] == 2 and c.params["n"] == (s["edge"], s["edge"], 1)
         assert abs(c.params["rho_h"] / c.params["rho_l"] - s["rho_ratio"]) < 1e-9 * s["rho_ratio"]
         assert 0.0 <= c.phi.min() and c.phi.max() <= 1.0
+
+
+def test_splash2d_is_mirror_symmetric_with_the_paper_parameters():
+    c = inputs.splash2d(D=40.0, Re=1000.0, We=2200.0)
+    assert c.params["bc"] == (inputs.BC_SYMMETRY, inputs.BC_WALL, inputs.BC_PERIODIC)
+    assert c.params["n"] == (320, 160, 1)
+    # density ratio 1000 and viscosity ratio 15 (Sec. 3.4)
+    assert abs(c.params["rho_h"] / c.params["rho_l"] - 1000.0) < 1e-9
+    assert abs(c.params["nu_l"] / c.params["nu_h"] - 15.0) < 1e-12
+    # Re = rho_h U0 D / mu_h, We = rho_liquid D U0^2 / sigma, K = We^1/2 Re^1/4
+    assert abs(0.05 * 40.0 / c.params["nu_h"] - 1000.0) < 1e-9
+    assert abs(40.0 * 0.05 ** 2 / c.params["sigma"] - 2200.0) < 1e-9
+    assert abs(c.meta["K"] - 2200.0 ** 0.5 * 1000.0 ** 0.25) < 1e-9
+    # mirror symmetry about the box axis, for phi and u_y; u_x = 0
+    assert np.array_equal(c.phi[0], c.phi[0][:, ::-1])
+    assert np.array_equal(c.u[1, 0], c.u[1, 0][:, ::-1]) and not c.u[0].any()
