@@ -578,7 +578,8 @@ int upload_tables(mplb_batch *b)
     for (int i = 0; i < b->capacity; ++i)
         if (b->slot[i])
             fused = fused && mplb::fused_ok_geom(b->dim, b->collision, b->doms[i].g);
-    const int bx = b->block.x, by = b->block.y, bz = b->block.z;
+    const int threads = int(b->block.x * b->block.y * b->block.z);
+    bool row = true;
     for (int i = 0; i < b->capacity; ++i) {
         const mplb_solver *s = b->slot[i];
         if (!s) continue;
@@ -590,18 +591,28 @@ int upload_tables(mplb_batch *b)
                 for (int z0 = 0; z0 < nz; z0 += zc) {
                     if ((long long)b->tiles.size() >= b->max_tiles)
                         return fail(MPLB_ENOMEM, "batch tile list is full");
-                    b->tiles.push_back(mplb::BatchTile{i, 0, y0, z0, z0 + zc < nz ? z0 + zc : nz});
+                    b->tiles.push_back(
+                        mplb::BatchTile{i, 0, y0, z0, z0 + zc < nz ? z0 + zc : nz, 0});
                 }
             continue;
         }
-        // block tiles (one block depth in z)
-        const int zt = bz;
-        for (int z0 = 0; z0 < nz; z0 += zt)
-            for (int y0 = 0; y0 < ny; y0 += by)
-                for (int x0 = 0; x0 < nx; x0 += bx) {
+        // tile width: the domain's row rounded up to a power of two, at least
+        // 64 where the row form can apply (x periodic), at most the block's
+        // width; the rest of the block's threads cover further rows
+        int w = 1;
+        while (w < nx) w <<= 1;
+        const bool xper = b->doms[i].g.bcx == mplb::BC_PER;
+        if (xper && w < 64) w = 64;
+        if (w > int(b->block.x)) w = int(b->block.x);
+        if (w > threads) w = threads;
+        const int rows = threads / w;
+        row = row && mplb::row_form_ok(b->dim, b->doms[i].g, dim3(w, rows, 1));
+        for (int z0 = 0; z0 < nz; ++z0)
+            for (int y0 = 0; y0 < ny; y0 += rows)
+                for (int x0 = 0; x0 < nx; x0 += w) {
                     if ((long long)b->tiles.size() >= b->max_tiles)
                         return fail(MPLB_ENOMEM, "batch tile list is full");
-                    b->tiles.push_back(mplb::BatchTile{i, x0, y0, z0, z0 + zt < nz ? z0 + zt : nz});
+                    b->tiles.push_back(mplb::BatchTile{i, x0, y0, z0, z0 + 1, w});
                 }
     }
     if (fused != b->fused) drop_graph(b);
@@ -616,9 +627,6 @@ int upload_tables(mplb_batch *b)
         if (grid != b->grid) drop_graph(b);
         b->grid = grid;
     }
-    bool row = true;
-    for (int i = 0; i < b->capacity; ++i)
-        if (b->slot[i]) row = row && mplb::row_form_ok(b->dim, b->doms[i].g, b->block);
     if (row != b->row) drop_graph(b);  // a captured graph holds the other kernel
     b->row = row;
     HIPCHK(hipStreamSynchronize(b->stream));

@@ -91,11 +91,12 @@ struct BatchDom {
     long long first, last;  // active for batch steps first <= t < last
 };
 
-// A tile of a batch: domain index, origin cell (x0, y0, z0) and the end of
-// its plane range z1: a block-shaped tile repeated along z up to z1, or, for
-// the fused kernels, whole rows y0 .. y0 + rows - 1 over planes z0 .. z1 - 1.
+// A tile of a batch: domain index, origin cell (x0, y0, z0), end of its
+// plane range z1 and width w: w cells in x by (threads per block) / w rows,
+// one plane; for the fused kernels whole rows y0 .. y0 + rows - 1 over
+// planes z0 .. z1 - 1 (w unused).
 struct BatchTile {
-    int dom, x0, y0, z0, z1;
+    int dom, x0, y0, z0, z1, w;
 };
 
 // One step of every active domain: persistent blocks stride over the tile

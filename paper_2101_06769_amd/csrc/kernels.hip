@@ -1089,8 +1089,14 @@ __attribute__((amdgpu_waves_per_eu(PHI ? 1 : collide_waves<D, P, COLL>()))) kb_s
         const long long first = doms[tl.dom].first, last = doms[tl.dom].last;
         if (t < first || t >= last) continue;
         const Ptrs p = batch_ptrs(doms[tl.dom], int((t - first) & 1));
-        int x, y, z;
-        thread_cell<ROW>(tl.x0, tl.y0, tl.z0, x, y, z);
+        // the tile is tl.w cells wide in x and (block threads) / tl.w rows
+        // high, one plane deep; the width is the domain's own (a multiple of
+        // 64 in the row form, so that each wavefront lies in one x-row)
+        const int tid = int(threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z));
+        const int x = tl.x0 + tid % tl.w;
+        int y = tl.y0 + tid / tl.w;
+        const int z = tl.z0;
+        if constexpr (ROW) y = __builtin_amdgcn_readfirstlane(y);
         if (x >= g.nx || y >= g.ny || z >= tl.z1) continue;
         if constexpr (PHI) {
             phi_cell<D, P, NbOf<ROW>>(g, p, x, y, z);
