@@ -50,6 +50,7 @@ class Params(ctypes.Structure):
         ("rate4", ctypes.c_double),
         ("rate5", ctypes.c_double),
         ("rate6", ctypes.c_double),
+        ("cac_edf", ctypes.c_int),
     ]
 
 
@@ -81,12 +82,13 @@ def _load():
         lib.orc_gradients.argtypes = [pp, dp, dp, dp]
         lib.orc_init.argtypes = [pp, dp, dp, dp, dp, dp]
         lib.orc_step.argtypes = [pp, dp, dp, dp, dp]
+        lib.orc_step_hist.argtypes = [pp, dp, dp, dp, dp, dp, ctypes.c_int]
         lib.orc_step_sampled.argtypes = [pp, dp, dp, ctypes.POINTER(ctypes.c_long), ctypes.c_long,
                                          dp, dp]
         lib.orc_fields.argtypes = [pp, dp, dp, dp, dp, dp, dp]
         lib.orc_reduce.argtypes = [pp, dp, dp, dp]
         lib.orc_collide_cell.argtypes = [pp, dp, dp, ctypes.c_double, dp, ctypes.c_double, dp, dp,
-                                         dp]
+                                         dp, dp, dp]
         lib.orc_central_moments.argtypes = [ctypes.c_int, dp, dp, dp]
         lib.orc_cumulants_from_central.argtypes = [ctypes.c_int, dp, dp]
         lib.orc_central_from_cumulants.argtypes = [ctypes.c_int, dp, dp]
@@ -104,7 +106,7 @@ def _ptr(a):
 
 def make_params(dim, n, bc=(0, 0, 0), rho_h=1.0, rho_l=1.0, nu_h=0.1, nu_l=None, W=4.0, M=0.1,
                 sigma=0.0, g=(0.0, 0.0, 0.0), visc_interp=0, collision=COLL_CUMULANT,
-                rate_bulk=1.0, rate3=1.0, rate4=1.0, rate5=1.0, rate6=1.0) -> Params:
+                rate_bulk=1.0, rate3=1.0, rate4=1.0, rate5=1.0, rate6=1.0, cac_edf=0) -> Params:
     p = Params()
     p.dim = dim
     nn = list(n) + [1] * (3 - len(n))
@@ -119,13 +121,15 @@ def make_params(dim, n, bc=(0, 0, 0), rho_h=1.0, rho_l=1.0, nu_h=0.1, nu_l=None,
     p.visc_interp, p.collision = int(visc_interp), int(collision)
     p.rate_bulk, p.rate3, p.rate4, p.rate5, p.rate6 = map(float, (rate_bulk, rate3, rate4, rate5,
                                                                   rate6))
+    p.cac_edf = int(cac_edf)
     return p
 
 
 def params_from_dict(d: dict) -> Params:
     """Build oracle parameters from a plain case dictionary (keys as in make_params)."""
     keys = ("dim", "n", "bc", "rho_h", "rho_l", "nu_h", "nu_l", "W", "M", "sigma", "g",
-            "visc_interp", "collision", "rate_bulk", "rate3", "rate4", "rate5", "rate6")
+            "visc_interp", "collision", "rate_bulk", "rate3", "rate4", "rate5", "rate6",
+            "cac_edf")
     return make_params(**{k: d[k] for k in keys if k in d})
 
 
@@ -180,15 +184,30 @@ def init(p: Params, phi, u, ph):
 
 
 def step(p: Params, f, g, nsteps: int = 1):
+    """nsteps steps from (f, g).  With the first-order phase-field equilibrium
+    the first step has no (phi u) history (zero time derivative) and later
+    steps carry it."""
+    f, g, _ = step_hist(p, f, g, nsteps, None)
+    return f, g
+
+
+def step_hist(p: Params, f, g, nsteps: int = 1, phiu=None):
+    """As step, with the (phi u) history: phiu ([3][nz][ny][nx], or None for
+    no history) is that of the step before (f, g); returns (f, g, phiu)."""
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     g = np.array(g, dtype=np.float64, order="C", copy=True)
     fo = np.empty_like(f)
     go = np.empty_like(g)
+    have = phiu is not None
+    h = (np.array(phiu, dtype=np.float64, order="C", copy=True) if have
+         else np.zeros((3,) + _shape(p)))
     for _ in range(nsteps):
-        _check(_load().orc_step(ctypes.byref(p), _ptr(f), _ptr(g), _ptr(fo), _ptr(go)))
+        _check(_load().orc_step_hist(ctypes.byref(p), _ptr(f), _ptr(g), _ptr(fo), _ptr(go),
+                                     _ptr(h), 1 if have else 0))
+        have = True
         f, fo = fo, f
         g, go = go, g
-    return f, g
+    return f, g, h
 
 
 def step_sampled(p: Params, f, g, cells):
@@ -222,7 +241,9 @@ def reduce(p: Params, f, g):
     return out
 
 
-def collide_cell(p: Params, f, g, phi, grad, lap):
+def collide_cell(p: Params, f, g, phi, grad, lap, phiu_prev=None):
+    """One cell's collision; phiu_prev is the cell's (phi u) of the previous
+    step for the first-order phase-field equilibrium (None: no history)."""
     q = Q(p.dim)
     f = np.ascontiguousarray(f, dtype=np.float64)
     g = np.ascontiguousarray(g, dtype=np.float64)
@@ -231,8 +252,11 @@ def collide_cell(p: Params, f, g, phi, grad, lap):
     fo = np.zeros(q)
     go = np.zeros(q)
     dg = np.zeros(DIAG_SIZE)
+    prev = None if phiu_prev is None else np.ascontiguousarray(phiu_prev, dtype=np.float64)
+    out = np.zeros(3)
     _check(_load().orc_collide_cell(ctypes.byref(p), _ptr(f), _ptr(g), float(phi), _ptr(gr),
-                                    float(lap), _ptr(fo), _ptr(go), _ptr(dg)))
+                                    float(lap), _ptr(fo), _ptr(go), _ptr(dg), _ptr(prev),
+                                    _ptr(out)))
     return fo, go, dg
 
 

@@ -149,6 +149,7 @@ static int check_params(const orc_params *p)
     if (p->dim != 2 && p->dim != 3) return -1;
     if (p->n[0] <= 0 || p->n[1] <= 0 || p->n[2] <= 0) return -1;
     if (p->dim == 2 && p->n[2] != 1) return -1;
+    if (p->cac_edf != 0 && p->cac_edf != 1) return -1;
     return 0;
 }
 
@@ -169,6 +170,16 @@ static double hermite_sum(const int *c, const double *u, int nmin)
         for (j = 0; j < 3; j++) h2 += (c[i] * c[j] - CS2 * (i == j)) * u[i] * u[j];
     s += h2 / (2.0 * CS2 * CS2);
     return s;
+}
+
+/* The same expansion truncated after the first-order term (Sec. 2.2, the
+ * first-order equilibrium): 1 + c.u / cs^2. */
+static double hermite_sum_first(const int *c, const double *u)
+{
+    double h1 = 0.0;
+    int i;
+    for (i = 0; i < 3; i++) h1 += c[i] * u[i];
+    return 1.0 + h1 / CS2;
 }
 
 /* ----------------------------------------------------------------------- */
@@ -447,7 +458,8 @@ static void relax_cumulants(const orc_params *p, double omega, const double *K, 
 /* (Sec. 2.2).                                                              */
 /* ----------------------------------------------------------------------- */
 int orc_collide_cell(const orc_params *p, const double *f, const double *g, double phi,
-                     const double *grad, double lap, double *fo, double *go, double *diag)
+                     const double *grad, double lap, double *fo, double *go, double *diag,
+                     const double *phiu_prev, double *phiu_out)
 {
     lat_t L;
     double rho, grad_rho[3], beta, kappa, mu, F[3], nrm, n[3], nu, tau, omega;
@@ -546,16 +558,35 @@ int orc_collide_cell(const orc_params *p, const double *f, const double *g, doub
         }
     }
 
-    /* conservative Allen-Cahn: BGK with second-order equilibrium and the
-     * discrete antidiffusion source */
+    /* conservative Allen-Cahn: BGK toward the equilibrium, plus the discrete
+     * antidiffusion source (Sec. 2.2).  With the first-order equilibrium the
+     * discrete correction term Cbar = (1 - 1/(2 taubar)) (w / cs^2) c.d(phi u)/dt
+     * is added; the time derivative is the backward difference over one step
+     * (zero when no previous (phi u) is given). */
     tau_phi = p->M / CS2;
     tpb = tau_phi + 0.5;
-    for (a = 0; a < Q; a++) {
-        double cn = 0.0;
-        for (i = 0; i < 3; i++) cn += L.c[a][i] * n[i];
-        geq[a] = L.w[a] * phi * hermite_sum(L.c[a], u, 0);
-        Sbar[a] = (1.0 - 1.0 / (2.0 * tpb)) * L.w[a] * cn * 4.0 * phi * (1.0 - phi) / p->W;
-        go[a] = (1.0 - 1.0 / tpb) * g[a] + geq[a] / tpb + Sbar[a];
+    {
+        double phiu[3], dphiu[3];
+        for (i = 0; i < 3; i++) {
+            phiu[i] = phi * u[i];
+            dphiu[i] = (p->cac_edf == 1 && phiu_prev) ? phiu[i] - phiu_prev[i] : 0.0;
+            if (phiu_out) phiu_out[i] = phiu[i];
+        }
+        for (a = 0; a < Q; a++) {
+            double cn = 0.0, cd = 0.0, Cbar = 0.0;
+            for (i = 0; i < 3; i++) {
+                cn += L.c[a][i] * n[i];
+                cd += L.c[a][i] * dphiu[i];
+            }
+            if (p->cac_edf == 1) {
+                geq[a] = L.w[a] * phi * hermite_sum_first(L.c[a], u);
+                Cbar = (1.0 - 1.0 / (2.0 * tpb)) * L.w[a] / CS2 * cd;
+            } else {
+                geq[a] = L.w[a] * phi * hermite_sum(L.c[a], u, 0);
+            }
+            Sbar[a] = (1.0 - 1.0 / (2.0 * tpb)) * L.w[a] * cn * 4.0 * phi * (1.0 - phi) / p->W;
+            go[a] = (1.0 - 1.0 / tpb) * g[a] + geq[a] / tpb + Sbar[a] + Cbar;
+        }
     }
 
     if (diag) {
@@ -674,6 +705,12 @@ static void gather_cell(const double *arr, long N, int Q, long idx, double *out)
 
 int orc_step(const orc_params *p, const double *f, const double *g, double *fo, double *go)
 {
+    return orc_step_hist(p, f, g, fo, go, NULL, 0);
+}
+
+int orc_step_hist(const orc_params *p, const double *f, const double *g, double *fo, double *go,
+                  double *phiu, int have_prev)
+{
     lat_t L;
     long N;
     double *phi, *fs, *gs;
@@ -708,7 +745,17 @@ int orc_step(const orc_params *p, const double *f, const double *g, double *fo, 
             stencil(p, &L, phi, NULL, x, y, z, &p0, gr, &lp);
             gather_cell(f, N, L.Q, idx, fc);
             gather_cell(g, N, L.Q, idx, gc);
-            err |= orc_collide_cell(p, fc, gc, p0, gr, lp, fpost, gpost, NULL);
+            {
+                double prev[3], cur[3];
+                int i;
+                if (phiu && have_prev)
+                    for (i = 0; i < 3; i++) prev[i] = phiu[(long)i * N + idx];
+                err |= orc_collide_cell(p, fc, gc, p0, gr, lp, fpost, gpost, NULL,
+                                        (phiu && have_prev) ? prev : NULL, cur);
+                /* each cell reads only its own previous value: update in place */
+                if (phiu)
+                    for (i = 0; i < 3; i++) phiu[(long)i * N + idx] = cur[i];
+            }
             for (a = 0; a < L.Q; a++) {
                 fs[(long)a * N + idx] = fpost[a];
                 gs[(long)a * N + idx] = gpost[a];
@@ -763,7 +810,7 @@ int orc_step_sampled(const orc_params *p, const double *f, const double *g, cons
             stencil(p, &L, NULL, g, sx, sy, sz, &p0, gr, &lp);
             gather_cell(f, N, L.Q, sc, fc);
             gather_cell(g, N, L.Q, sc, gc);
-            err |= orc_collide_cell(p, fc, gc, p0, gr, lp, fpost, gpost, NULL);
+            err |= orc_collide_cell(p, fc, gc, p0, gr, lp, fpost, gpost, NULL, NULL, NULL);
             fo[k * L.Q + a] = fpost[sd];
             go[k * L.Q + a] = gpost[sd];
         }
@@ -800,7 +847,7 @@ int orc_fields(const orc_params *p, const double *f, const double *g, double *ph
             stencil(p, &L, phf, NULL, x, y, z, &p0, gr, &lp);
             gather_cell(f, N, L.Q, idx, fc);
             gather_cell(g, N, L.Q, idx, gc);
-            err |= orc_collide_cell(p, fc, gc, p0, gr, lp, fpost, gpost, dg);
+            err |= orc_collide_cell(p, fc, gc, p0, gr, lp, fpost, gpost, dg, NULL, NULL);
             if (phi) phi[idx] = p0;
             if (rho) rho[idx] = dg[D_RHO];
             if (u)

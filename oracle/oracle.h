@@ -36,6 +36,9 @@ typedef struct {
     int collision;      /* ORC_COLL_* */
     /* relaxation rates of the non-viscous cumulant groups (all 1 in the paper) */
     double rate_bulk, rate3, rate4, rate5, rate6;
+    /* phase-field equilibrium: 0 second-order (the paper's choice); 1
+     * first-order plus the correction term of Sec. 2.2 */
+    int cac_edf;
 } orc_params;
 
 /* number of diag doubles written by orc_collide_cell */
@@ -50,6 +53,12 @@ int orc_gradients(const orc_params *p, const double *phi, double *grad, double *
 int orc_init(const orc_params *p, const double *phi, const double *u, const double *ph,
              double *f, double *g);
 int orc_step(const orc_params *p, const double *f, const double *g, double *fo, double *go);
+/* One step with the history the first-order phase-field equilibrium needs:
+ * phiu holds (phi u) per cell ([3][N]) of the previous step when have_prev
+ * is non-zero, and receives this step's; without history the time
+ * derivative of (phi u) is taken as zero. */
+int orc_step_hist(const orc_params *p, const double *f, const double *g, double *fo, double *go,
+                  double *phiu, int have_prev);
 int orc_step_sampled(const orc_params *p, const double *f, const double *g,
                      const long *cells, long m, double *fo, double *go);
 int orc_fields(const orc_params *p, const double *f, const double *g,
@@ -57,7 +66,8 @@ int orc_fields(const orc_params *p, const double *f, const double *g,
 int orc_reduce(const orc_params *p, const double *f, const double *g, double *out5);
 
 int  orc_collide_cell(const orc_params *p, const double *f, const double *g, double phi,
-                      const double *grad, double lap, double *fo, double *go, double *diag);
+                      const double *grad, double lap, double *fo, double *go, double *diag,
+                      const double *phiu_prev, double *phiu_out);
 void orc_central_moments(int dim, const double *h, const double *u, double *Pi27);
 void orc_cumulants_from_central(int dim, const double *Pi27, double *K27);
 void orc_central_from_cumulants(int dim, const double *K27, double *Pi27);
