@@ -112,7 +112,11 @@ typedef struct mplb_params {
     int32_t storage;      /* MPLB_STORE_* */
     int32_t visc_interp;  /* 0: nu = nu_l + (nu_h - nu_l) phi; 1: rho nu linear in phi */
     int32_t collision;    /* MPLB_COLL_* */
-    int32_t reserved;     /* must be 0 */
+    int32_t cac_edf;      /* phase-field equilibrium (Sec. 2.2): 0 second-order (the
+                             paper's); 1 first-order plus the correction term
+                             (1 - 1/(2 taubar_phi)) (w/cs^2) c.d(phi u)/dt, the time
+                             derivative the backward difference over one step (zero on
+                             the first step after mplb_init / mplb_set_populations) */
 } mplb_params;
 
 typedef struct mplb_solver mplb_solver;

@@ -46,7 +46,7 @@ struct Layout {
     int Q;
     long long N, np;
     size_t sF, sG, sT;
-    size_t F[2], G[2], phi, fp[2], fr[2], gp[2], partials, result, total;
+    size_t F[2], G[2], phi, fp[2], fr[2], gp[2], phiu[2], partials, result, total;
     size_t staging_bytes;
 };
 
@@ -76,7 +76,7 @@ bool validate(const mplb_params *p, std::string &why)
     if (p->visc_interp != 0 && p->visc_interp != 1) return why = "visc_interp must be 0 or 1", false;
     if (p->collision != MPLB_COLL_CUMULANT && p->collision != MPLB_COLL_SRT)
         return why = "unknown collision operator", false;
-    if (p->reserved != 0) return why = "reserved must be 0", false;
+    if (p->cac_edf != 0 && p->cac_edf != 1) return why = "cac_edf must be 0 or 1", false;
     return true;
 }
 
@@ -113,6 +113,15 @@ Layout make_layout(const mplb_params *p)
         if (p->storage == MPLB_STORE_FP16S_ALL) {
             L.gp[k] = off;
             off += bref;
+        }
+    }
+    // (phi u) of the current and previous step, [3][np] in the arithmetic
+    // type, for the first-order phase-field equilibrium only
+    for (int k = 0; k < 2; ++k) {
+        L.phiu[k] = 0;
+        if (p->cac_edf) {
+            L.phiu[k] = off;
+            off += up(3 * L.np * L.sT, ALIGN);
         }
     }
     L.partials = off;
@@ -159,6 +168,7 @@ mplb::PhysD make_phys(const mplb_params *p)
     d.four_W = 4.0 / p->W;
     d.visc_interp = p->visc_interp;
     d.collision = p->collision;
+    d.cac_edf = p->cac_edf;
     return d;
 }
 
@@ -173,6 +183,7 @@ struct mplb_solver {
     int64_t steps;
     bool ready;
     bool attached;
+    bool hist;  // (phi u) of the previous step is stored (first-order phase-field equilibrium)
     int fuse;  // one-launch step: 0 never, 1 where faster (FP16 formats), 2 where it applies
     dim3 block;
     mplb::PhysD ph;
@@ -213,6 +224,9 @@ struct mplb_solver {
         c.p.fp_out = static_cast<float *>(at(L.fp[1 - in]));
         c.p.fr_out = static_cast<float *>(at(L.fr[1 - in]));
         c.p.gp_out = static_cast<float *>(at(L.gp[1 - in]));
+        c.p.phiu_in = at(L.phiu[in]);
+        c.p.phiu_out = at(L.phiu[1 - in]);
+        c.p.have_prev = hist ? 1 : 0;
         return c;
     }
 
@@ -367,6 +381,7 @@ int mplb_init(mplb_solver *s, const double *phi, const double *u, const double *
     s->cur = 0;
     s->steps = 0;
     s->ready = true;
+    s->hist = false;
     return MPLB_OK;
 }
 
@@ -386,6 +401,7 @@ int mplb_step(mplb_solver *s, int64_t nsteps)
         }
         s->cur ^= 1;
         s->steps++;
+        s->hist = true;
     }
     return MPLB_OK;
 }
@@ -412,6 +428,7 @@ int mplb_step_timed(mplb_solver *s, int64_t nsteps, double *ms_phi, double *ms_c
             if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 2], s->stream);
             s->cur ^= 1;
             s->steps++;
+            s->hist = true;
         }
         if (e == hipSuccess) e = hipEventSynchronize(ev[2 * k]);
         for (int i = 0; i < k && e == hipSuccess; ++i) {
@@ -515,6 +532,7 @@ int mplb_set_populations(mplb_solver *s, int32_t which, const double *host_in)
     }
     s->ready = true;
     s->steps = 0;
+    s->hist = false;
     return MPLB_OK;
 }
 
@@ -577,7 +595,7 @@ int upload_tables(mplb_batch *b)
     bool fused = b->fuse == 2 || (b->fuse == 1 && mplb::fused_preferred(b->storage));
     for (int i = 0; i < b->capacity; ++i)
         if (b->slot[i])
-            fused = fused && mplb::fused_ok_geom(b->dim, b->collision, b->doms[i].g);
+            fused = fused && mplb::fused_ok_geom(b->dim, b->collision & 1, b->doms[i].g);
     const int threads = int(b->block.x * b->block.y * b->block.z);
     bool row = true;
     for (int i = 0; i < b->capacity; ++i) {
@@ -744,11 +762,14 @@ int mplb_batch_attach(mplb_batch *b, mplb_solver *s, int64_t nsteps, int32_t *sl
         return fail(MPLB_EINVAL, "solver dimension/storage differ from the batch's");
     bool empty = true;
     for (auto *o : b->slot) empty = empty && !o;
+    // operator code: flow collision (bit 0), first-order phase-field equilibrium (bit 1)
+    const int code = s->prm.collision | (s->prm.cac_edf << 1);
     if (empty) {
-        if (b->collision != s->prm.collision) drop_graph(b);
-        b->collision = s->prm.collision;
-    } else if (s->prm.collision != b->collision) {
-        return fail(MPLB_EINVAL, "solvers of one batch must share the collision operator");
+        if (b->collision != code) drop_graph(b);
+        b->collision = code;
+    } else if (code != b->collision) {
+        return fail(MPLB_EINVAL,
+                    "solvers of one batch must share the collision operator and phase-field equilibrium");
     }
     if (s->stream != b->stream) return fail(MPLB_EINVAL, "solver and batch streams differ");
     if (!s->ready) return fail(MPLB_ESTATE, "solver is not initialised");
@@ -770,7 +791,10 @@ int mplb_batch_attach(mplb_batch *b, mplb_solver *s, int64_t nsteps, int32_t *sl
         d.fp[j] = static_cast<float *>(s->at(s->L.fp[j]));
         d.fr[j] = static_cast<float *>(s->at(s->L.fr[j]));
         d.gp[j] = static_cast<float *>(s->at(s->L.gp[j]));
+        d.phiu[j] = s->at(s->L.phiu[j]);
     }
+    // the domain's first batch step is b->t: history from there if it has one
+    d.hist_from = s->hist ? b->t : b->t + 1;
     d.phi = s->base + s->L.phi;
     // input buffer at batch step t is (t - first) & 1; at t = b->t it is s->cur
     d.first = b->t - s->cur;
@@ -868,6 +892,7 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
         const long long adv = hi > lo ? hi - lo : 0;
         s->steps += adv;
         s->cur = int((s->cur + adv) & 1);
+        if (adv > 0) s->hist = true;
     }
     return MPLB_OK;
 }

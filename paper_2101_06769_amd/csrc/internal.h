@@ -23,6 +23,7 @@ struct PhysD {
     double four_W;         // 4 / W
     int visc_interp;
     int collision;         // 0 cumulant, 1 SRT
+    int cac_edf;           // phase-field equilibrium: 0 second-order, 1 first-order + correction
 };
 
 // Device buffers one launch works on.  "in" buffers hold the post-collision
@@ -39,6 +40,11 @@ struct Ptrs {
     float *fp_out, *fr_out;
     const float *gp_in;           // g: phi shift
     float *gp_out;
+    // first-order phase-field equilibrium: (phi u) per cell, [3][np], of the
+    // previous step (valid when have_prev) and of this step
+    const void *phiu_in;
+    void *phiu_out;
+    int have_prev;
 };
 
 struct Ctx {
@@ -88,7 +94,9 @@ struct BatchDom {
     PhysD ph;
     void *F[2], *G[2], *phi;
     float *fp[2], *fr[2], *gp[2];
+    void *phiu[2];
     long long first, last;  // active for batch steps first <= t < last
+    long long hist_from;    // (phi u) of the previous step valid for t >= hist_from
 };
 
 // A tile of a batch: domain index, origin cell (x0, y0, z0), end of its
@@ -105,7 +113,8 @@ struct BatchTile {
 // x periodic, population arrays of fewer than 2^31 elements.
 bool row_form_ok(int dim, const Geom &g, dim3 block);
 // row: every attached domain satisfies row_form_ok with this block.
-// fused: one kernel per step over fused tiles (every attached domain
+// collision: operator code, bit 0 the flow collision, bit 1 the first-order
+// phase-field equilibrium.  fused: one kernel per step over fused tiles (every attached domain
 // satisfies fused_ok_geom); else the phi pass and the update over block
 // tiles.  The blocks stride over the tile list: fixed_grid > 0 launches that
 // many blocks (at least one per tile: hardware scheduling), else a persistent

@@ -180,7 +180,7 @@ __device__ __forceinline__ T phi_at(const NbRow &n, const T *phi, int cx, int cy
 template <typename T>
 struct Phys {
     T rho_l, drho, nu_l, dnu, rnu_l, drnu, beta, kappa, gx, gy, gz, inv_tpb, src_pre, four_W;
-    int visc_interp, collision;
+    int visc_interp, collision, cac_edf;
 };
 
 template <typename T>
@@ -203,6 +203,7 @@ __host__ __device__ static Phys<T> to_phys(const PhysD &d)
     p.four_W = T(d.four_W);
     p.visc_interp = d.visc_interp;
     p.collision = d.collision;
+    p.cac_edf = d.cac_edf;
     return p;
 }
 
@@ -501,7 +502,9 @@ template <int D, class P, bool ROW>
 __global__ void __launch_bounds__(256) k_phi(Geom g, Ptrs p);
 
 // The fused update of one cell: stencil, closure, flow collision, phase-field
-// collision; post-collision values stored at the cell.
+// collision; post-collision values stored at the cell.  COLL bit 0: flow
+// collision (0 cumulant, 1 single relaxation time); bit 1: first-order
+// phase-field equilibrium with the correction term.
 template <int D, class P, int COLL, class NB>
 __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
                                              const Phys<typename P::T> &ph, const Ptrs &p)
@@ -521,7 +524,7 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
     const T V = c.ux * c.Fx + c.uy * c.Fy + c.uz * c.Fz;
     const T rcs2 = c.rho * cs2;
 
-    if constexpr (COLL == 0) {
+    if constexpr ((COLL & 1) == 0) {
         // second moments of Xi in closed form (4th-order isotropy of the lattice)
         auto xim = [&](T ui, T uj, T gi, T gj, T Fi, T Fj, bool diag) {
             return cs2 * (cs2 * ((diag ? c.U : T(0)) + ui * gj + uj * gi) - ui * uj * c.U) +
@@ -622,7 +625,10 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
     const T nrm = sqrt(c.gx * c.gx + c.gy * c.gy + c.gz * c.gz + T(1e-24));
     const T nx = c.gx / nrm, ny = c.gy / nrm, nz = c.gz / nrm;
     const T src = ph.src_pre * ph.four_W * c.phi * (T(1) - c.phi);
-    // g_eq = phi Gamma: a direction and its opposite together.
+    // g_eq = phi Gamma: a direction and its opposite together.  With the
+    // first-order equilibrium (Sec. 2.2) g_eq = w phi (1 + c.u / cs^2) and the
+    // correction (1 - 1/(2 taubar)) (w / cs^2) c.d(phi u)/dt is added, the time
+    // derivative the backward difference of the cell's (phi u) over one step.
     const T gbase = T(1) - T(1.5) * usq;
     T gsum = 0;
     auto gemit = [&](int a, T gout) {
@@ -635,27 +641,53 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
                 lane_ptr(static_cast<typename P::G::raw *>(p.Gout), (long long)a * g.np + row, xl));
         }
     };
+    auto cac = [&](auto first_order) {
+        constexpr bool E1 = decltype(first_order)::value;
+        T dx = 0, dy = 0, dz = 0;
+        if constexpr (E1) {
+            T *out = static_cast<T *>(p.phiu_out);
+            const T *in = static_cast<const T *>(p.phiu_in);
+            const T qx = c.phi * c.ux, qy = c.phi * c.uy, qz = c.phi * c.uz;
+            if (p.have_prev) {
+                dx = qx - *lane_ptr(in, row, xl);
+                dy = qy - *lane_ptr(in, g.np + row, xl);
+                dz = qz - *lane_ptr(in, 2 * g.np + row, xl);
+            }
+            *lane_ptr(out, row, xl) = qx;
+            *lane_ptr(out, g.np + row, xl) = qy;
+            *lane_ptr(out, 2 * g.np + row, xl) = qz;
+        }
 #pragma unroll
-    for (int a = Q / 2 + 1; a < Q; ++a) {
-        const int b = opposite<D>(a);
-        const T w = weight<D, T>(a);
-        const T va = pull<D, typename P::G, T>(nb, p.Gin, g.np, a, p.gp_in, nullptr);
-        const T vb = pull<D, typename P::G, T>(nb, p.Gin, g.np, b, p.gp_in, nullptr);
-        const T cu = cdot<D>(a, c.ux, c.uy, c.uz);
-        T ga, gb;
-        gamma_pair(w, gbase, cu, ga, gb);
-        const T s = w * cdot<D>(a, nx, ny, nz) * src;
-        gemit(a, va + (c.phi * ga - va) * ph.inv_tpb + s);
-        gemit(b, vb + (c.phi * gb - vb) * ph.inv_tpb - s);
-    }
-    if constexpr (P::G::shifted) {
-        constexpr int a0 = Q / 2;
-        const T v0 = pull<D, typename P::G, T>(nb, p.Gin, g.np, a0, p.gp_in, nullptr);
-        gemit(a0, v0 + (c.phi * weight<D, T>(a0) * gbase - v0) * ph.inv_tpb);
-    } else {
-        __builtin_nontemporal_store(typename P::G::raw(c.phi - gsum),
-            lane_ptr(static_cast<typename P::G::raw *>(p.Gout), (long long)(Q / 2) * g.np + row, xl));
-    }
+        for (int a = Q / 2 + 1; a < Q; ++a) {
+            const int b = opposite<D>(a);
+            const T w = weight<D, T>(a);
+            const T va = pull<D, typename P::G, T>(nb, p.Gin, g.np, a, p.gp_in, nullptr);
+            const T vb = pull<D, typename P::G, T>(nb, p.Gin, g.np, b, p.gp_in, nullptr);
+            const T cu = cdot<D>(a, c.ux, c.uy, c.uz);
+            T ga, gb;
+            T s = w * cdot<D>(a, nx, ny, nz) * src;
+            if constexpr (E1) {
+                const T o = T(3) * w * cu;
+                ga = w + o;
+                gb = w - o;
+                s += ph.src_pre * T(3) * w * cdot<D>(a, dx, dy, dz);
+            } else {
+                gamma_pair(w, gbase, cu, ga, gb);
+            }
+            gemit(a, va + (c.phi * ga - va) * ph.inv_tpb + s);
+            gemit(b, vb + (c.phi * gb - vb) * ph.inv_tpb - s);
+        }
+        if constexpr (P::G::shifted) {
+            constexpr int a0 = Q / 2;
+            const T v0 = pull<D, typename P::G, T>(nb, p.Gin, g.np, a0, p.gp_in, nullptr);
+            const T g0 = E1 ? weight<D, T>(a0) : weight<D, T>(a0) * gbase;
+            gemit(a0, v0 + (c.phi * g0 - v0) * ph.inv_tpb);
+        } else {
+            __builtin_nontemporal_store(typename P::G::raw(c.phi - gsum),
+                lane_ptr(static_cast<typename P::G::raw *>(p.Gout), (long long)(Q / 2) * g.np + row, xl));
+        }
+    };
+    cac(std::integral_constant<bool, (COLL & 2) != 0>{});
     if constexpr (P::G::shifted) *lane_ptr(p.gp_out, row, xl) = float(c.phi);
 }
 
@@ -1054,9 +1086,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double *part
 // The per-cell arithmetic is the single-domain path's (phi_cell,
 // collide_cell), so a domain's result does not depend on the batch it is in.
 
-__device__ __forceinline__ Ptrs batch_ptrs(const BatchDom &d, int in)
+__device__ __forceinline__ Ptrs batch_ptrs(const BatchDom &d, int in, bool have_prev)
 {
     Ptrs p;
+    p.phiu_in = d.phiu[in];
+    p.phiu_out = d.phiu[1 - in];
+    p.have_prev = have_prev ? 1 : 0;
     p.Fin = d.F[in];
     p.Gin = d.G[in];
     p.Fout = d.F[1 - in];
@@ -1088,7 +1123,7 @@ __attribute__((amdgpu_waves_per_eu(PHI ? 1 : collide_waves<D, P, COLL>()))) kb_s
         const Geom g = doms[tl.dom].g;
         const long long first = doms[tl.dom].first, last = doms[tl.dom].last;
         if (t < first || t >= last) continue;
-        const Ptrs p = batch_ptrs(doms[tl.dom], int((t - first) & 1));
+        const Ptrs p = batch_ptrs(doms[tl.dom], int((t - first) & 1), t >= doms[tl.dom].hist_from);
         // the tile is tl.w cells wide in x and (block threads) / tl.w rows
         // high, one plane deep; the width is the domain's own (a multiple of
         // 64 in the row form, so that each wavefront lies in one x-row)
@@ -1124,7 +1159,7 @@ kb_fused(const BatchDom *__restrict__ doms, const BatchTile *__restrict__ tiles,
         const Geom g = doms[tl.dom].g;  // by value, see kb_step
         const long long first = doms[tl.dom].first, last = doms[tl.dom].last;
         if (t < first || t >= last) continue;
-        const Ptrs p = batch_ptrs(doms[tl.dom], int((t - first) & 1));
+        const Ptrs p = batch_ptrs(doms[tl.dom], int((t - first) & 1), t >= doms[tl.dom].hist_from);
         const Phys<T> ph = to_phys<T>(doms[tl.dom].ph);
         fused_tile<D, P, COLL>(g, ph, p, tl.y0, tl.z0, tl.z1, sphi);
     }
@@ -1183,24 +1218,37 @@ hipError_t launch_phi(const Ctx &c)
     });
 }
 
+// Compile-time operator selection: bit 0 of COLL the flow collision, bit 1
+// the first-order phase-field equilibrium.
+static int coll_code(const PhysD &ph) { return (ph.collision ? 1 : 0) | (ph.cac_edf ? 2 : 0); }
+
+template <class Fn>
+static hipError_t with_coll(int code, Fn &&fn)
+{
+    switch (code) {
+    case 0: return fn(std::integral_constant<int, 0>{});
+    case 1: return fn(std::integral_constant<int, 1>{});
+    case 2: return fn(std::integral_constant<int, 2>{});
+    case 3: return fn(std::integral_constant<int, 3>{});
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_collide(const Ctx &c)
 {
     return dispatch(c, [&]<int D, class P>() {
         using T = typename P::T;
         const bool row = row_form(c);
-        if (c.ph.collision == 0 && row)
-            hipLaunchKernelGGL((k_collide<D, P, 0, true>), grid_for(c), c.block, 0, c.stream, c.g,
-                               to_phys<T>(c.ph), c.p);
-        else if (c.ph.collision == 0)
-            hipLaunchKernelGGL((k_collide<D, P, 0, false>), grid_for(c), c.block, 0, c.stream,
-                               c.g, to_phys<T>(c.ph), c.p);
-        else if (row)
-            hipLaunchKernelGGL((k_collide<D, P, 1, true>), grid_for(c), c.block, 0, c.stream, c.g,
-                               to_phys<T>(c.ph), c.p);
-        else
-            hipLaunchKernelGGL((k_collide<D, P, 1, false>), grid_for(c), c.block, 0, c.stream,
-                               c.g, to_phys<T>(c.ph), c.p);
-        return hipGetLastError();
+        return with_coll(coll_code(c.ph), [&](auto cc) {
+            constexpr int COLL = decltype(cc)::value;
+            if (row)
+                hipLaunchKernelGGL((k_collide<D, P, COLL, true>), grid_for(c), c.block, 0, c.stream,
+                                   c.g, to_phys<T>(c.ph), c.p);
+            else
+                hipLaunchKernelGGL((k_collide<D, P, COLL, false>), grid_for(c), c.block, 0,
+                                   c.stream, c.g, to_phys<T>(c.ph), c.p);
+            return hipGetLastError();
+        });
     });
 }
 
@@ -1242,8 +1290,12 @@ hipError_t launch_step_fused(const Ctx &c)
         if constexpr (D != 3) {
             return hipErrorInvalidValue;
         } else {
-            hipLaunchKernelGGL((k_fused<3, P, 0>), grid, dim3(FUSED_THREADS), 0, c.stream, c.g,
-                               to_phys<typename P::T>(c.ph), c.p, zc);
+            if (c.ph.cac_edf)
+                hipLaunchKernelGGL((k_fused<3, P, 2>), grid, dim3(FUSED_THREADS), 0, c.stream,
+                                   c.g, to_phys<typename P::T>(c.ph), c.p, zc);
+            else
+                hipLaunchKernelGGL((k_fused<3, P, 0>), grid, dim3(FUSED_THREADS), 0, c.stream,
+                                   c.g, to_phys<typename P::T>(c.ph), c.p, zc);
             return hipGetLastError();
         }
     });
@@ -1341,19 +1393,22 @@ hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool
         hipLaunchKernelGGL(k, dim3(grid), blk, 0, stream, doms, tiles, ntiles, tbase, step_off);
         return hipGetLastError();
     };
+    // collision: the operator code (bit 0 flow collision, bit 1 first-order
+    // phase-field equilibrium), shared by every domain of the batch
     return dispatch(c, [&]<int D, class P>() {
         if constexpr (D == 3) {
-            if (fused) return go(kb_fused<3, P, 0>, dim3(FUSED_THREADS), FUSED_THREADS);
+            if (fused && collision == 0) return go(kb_fused<3, P, 0>, dim3(FUSED_THREADS), FUSED_THREADS);
+            if (fused && collision == 2) return go(kb_fused<3, P, 2>, dim3(FUSED_THREADS), FUSED_THREADS);
         }
         if (fused) return hipErrorInvalidValue;
         hipError_t e = row ? go(kb_step<D, P, 0, true, true>, block, threads)
                            : go(kb_step<D, P, 0, true, false>, block, threads);
         if (e != hipSuccess) return e;
-        if (collision == 0)
-            return row ? go(kb_step<D, P, 0, false, true>, block, threads)
-                       : go(kb_step<D, P, 0, false, false>, block, threads);
-        return row ? go(kb_step<D, P, 1, false, true>, block, threads)
-                   : go(kb_step<D, P, 1, false, false>, block, threads);
+        return with_coll(collision, [&](auto cc) {
+            constexpr int COLL = decltype(cc)::value;
+            return row ? go(kb_step<D, P, COLL, false, true>, block, threads)
+                       : go(kb_step<D, P, COLL, false, false>, block, threads);
+        });
     });
 }
 

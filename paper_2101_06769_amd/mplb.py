@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
         ("storage", ctypes.c_int32),
         ("visc_interp", ctypes.c_int32),
         ("collision", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("cac_edf", ctypes.c_int32),
     ]
 
 
@@ -131,7 +131,7 @@ def make_params(d: dict, storage="fp32", collision=COLL_CUMULANT) -> Params:
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     p.visc_interp = int(d.get("visc_interp", 0))
     p.collision = int(d.get("collision", collision))
-    p.reserved = 0
+    p.cac_edf = int(d.get("cac_edf", 0))
     return p
 
 

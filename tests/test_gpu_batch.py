@@ -163,3 +163,26 @@ def test_batch_fused_and_two_kernel_forms_agree_bitwise():
         out.append([state(s) for s in solvers])
     for (fa, ga), (fb, gb) in zip(*out):
         assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
+def test_first_order_equilibrium_history_carries_into_a_batch():
+    # stepped alone for 2 steps (history built), then 3 steps in a batch: the
+    # batch must use the stored (phi u) on its first step, as stepping alone
+    cases = small_batch_cases(count=2, seed=47)
+    for c in cases:
+        c.params["cac_edf"] = 1
+    ref = []
+    for c in cases:
+        s = solver_for(c)
+        s.step(5)
+        ref.append(state(s))
+    b = mplb.Batch(3, "fp32", capacity=2, max_tiles=1 << 14)
+    b.set_graph_chunk(0)
+    solvers = [solver_for(c, stream=b.stream) for c in cases]
+    for s in solvers:
+        s.step(2)
+        b.attach(s, 3)
+    b.step(3)
+    for s, (fa, ga) in zip(solvers, ref):
+        fb, gb = state(s)
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb)

@@ -357,3 +357,40 @@ def test_fused_step_selection():
     s = gpu_solver(params, "fp32", fields=(phi, u, p))
     s.set_fused(2)
     assert not s.uses_fused()  # 2-D
+
+
+# First-order phase-field equilibrium with the correction term (Sec. 2.2):
+# from initialisation neither side has (phi u) history, so the first step has
+# no correction and later steps take the backward difference.
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("dim,n,bc", [CONFIGS[0], CONFIGS[3], CONFIGS[4], CONFIGS[6]])
+def test_first_order_phase_field_equilibrium_matches_oracle(storage, dim, n, bc):
+    params, phi, u, p = random_case(dim, n, bc, seed=41)
+    params["cac_edf"] = 1
+    po = oracle.params_from_dict(params)
+    f, g = oracle.init(po, phi, u, p)
+    s = gpu_solver(params, storage, fields=(phi, u, p))
+    s.step(1)
+    f1, g1 = oracle.step(po, f, g, 1)
+    assert rel_err(from_abi(dim, s.get_populations(1)), g1) < TOL1[storage]
+    s.step(2)
+    f3, g3 = oracle.step(po, f, g, 3)
+    assert rel_err(from_abi(dim, s.get_populations(0)), f3) < 10 * TOL1[storage]
+    assert rel_err(from_abi(dim, s.get_populations(1)), g3) < 10 * TOL1[storage]
+    # the correction is active: the second-order scheme differs
+    p2 = oracle.params_from_dict(dict(params, cac_edf=0))
+    _, g3b = oracle.step(p2, f, g, 3)
+    assert rel_err(g3b, g3) > 100 * TOL1[storage]
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+def test_first_order_equilibrium_fused_and_two_kernel_agree(storage):
+    params, phi, u, p = random_case(3, (70, 6, 5), (0, 1, 2), seed=43)
+    params["cac_edf"] = 1
+    out = []
+    for mode in (2, 0):
+        s = gpu_solver(params, storage, fields=(phi, u, p))
+        s.set_fused(mode)
+        s.step(4)
+        out.append((s.get_populations(0), s.get_populations(1)))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
