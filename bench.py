@@ -335,6 +335,56 @@ def bench_splash2d(args):
                       "results": out}), flush=True)
 
 
+def bench_edf(args):
+    """The two phase-field equilibria of Sec. 2.2 (second-order, the paper's;
+    first-order with the correction term): spike positions of the 2-D
+    Rayleigh-Taylor case (At 0.5, L = 300, Re 256 and 2048) to t/T = 5 under
+    each, and the step rate of each on the 128 x 128 x 512 3-D case (FP32)."""
+    import torch
+
+    from paper_2101_06769_amd import diagnostics, inputs, mplb
+
+    out = {}
+    for Re in (256.0, 2048.0):
+        rows = {}
+        for edf in (0, 1):
+            case = inputs.rti2d(nx=300, ny=1200, At=0.5, Re=Re, W=4.0, M=0.1, amp=30.0)
+            case.params["cac_edf"] = edf
+            T = case.meta["T"]
+            s = mplb.Solver(case.params, storage="fp32")
+            s.init(case.phi, case.u, case.p)
+            done, r = 0, []
+            for k in range(1, 11):
+                target = int(round(0.5 * k * T))
+                s.step(target - done)
+                done = target
+                spike, _ = diagnostics.rti_positions(s.read(0), 2)
+                r.append(None if spike is None else spike / 300.0)
+            rows[edf] = r
+        out["Re%d" % Re] = {"t_over_T": [0.5 * k for k in range(1, 11)],
+                            "spike_over_L_second_order": [round(v, 4) for v in rows[0]],
+                            "spike_over_L_first_order": [round(v, 4) for v in rows[1]],
+                            "max_difference": round(max(abs(a - b) for a, b in
+                                                        zip(rows[0], rows[1])), 4)}
+    case = inputs.rti3d()
+    rates = {}
+    for edf in (0, 1):
+        case.params["cac_edf"] = edf
+        s = mplb.Solver(case.params, storage="fp32")
+        s.init(case.phi, case.u, case.p)
+        s.step(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(300)
+        torch.cuda.synchronize()
+        rates["second_order" if edf == 0 else "first_order"] = round(
+            case.ncells * 300 / (time.perf_counter() - t0) / 1e6, 1)
+        del s
+    print(json.dumps({"workload": "phase-field equilibrium orders: 2-D RTI spike positions, "
+                                  "3-D RTI 128x128x512 MLUPS", "rti2d": out, "mlups_3d": rates}),
+          flush=True)
+
+
 def bench_serve(args):
     """Serving: seeded Poisson arrivals (20/s) of 2-D solves (Rayleigh-Taylor,
     static drop, impacting drop; edge log-uniform 64..1024, density ratio
@@ -392,7 +442,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="rti3d",
                     choices=["rti3d", "batch", "serve", "splash", "rti2d_convergence", "stability",
-                             "splash2d"],
+                             "splash2d", "edf"],
                     help="rti3d: the 128x128x512 step (default); batch: 64 uneven domains, "
                          "batched vs one per launch; serve: request replay; splash: "
                          "512x512x256 droplet impact in FP64 / FP32 / FP16")
@@ -429,6 +479,8 @@ def main():
         return bench_stability(args)
     if args.workload == "splash2d":
         return bench_splash2d(args)
+    if args.workload == "edf":
+        return bench_edf(args)
     if args.copy_probe:
         n = args.copy_probe << 20
         a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
