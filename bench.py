@@ -99,7 +99,7 @@ def bench_batch(args):
     edge in {32, 48, 64, 96, 128}, z = 4 edge, Atwood in [0.1, 0.9], Re in
     [100, 3000], random-phase multimode interface), FP32, `steps` steps each.
     Plain: one domain at a time, each with its own launches, on one stream.
-    Batched: all domains in the same persistent launches, block shape from the
+    Batched: all domains in the same launches, block shape from the
     autotuner, chunks of steps replayed as a HIP graph.  States are resident
     before either timed region starts; both start from the same initial state."""
     import torch

@@ -210,9 +210,8 @@ void mplb_destroy(mplb_solver *s);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent solvers of one dimension and storage format
- * advance together, two persistent launches per step over a tile list that
- * covers every attached lattice (each tile one block of the batch's block
- * shape).  Each attached solver has its own parameters, lattice size and
+ * advance together, two launches per step (one with the fused step) over a
+ * tile list that covers every attached lattice, one block per tile.  Each attached solver has its own parameters, lattice size and
  * activity window; a solver's result is identical whether it is stepped
  * alone or in a batch (same per-cell arithmetic).  Steps are replayed from a
  * captured hipGraph in chunks of `graph_chunk` steps.

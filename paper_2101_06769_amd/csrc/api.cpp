@@ -553,7 +553,7 @@ struct mplb_batch {
     std::vector<mplb::BatchDom> doms;
     std::vector<mplb::BatchTile> tiles;
     int ntiles_host;
-    int grid;     // blocks per launch: tile count rounded up to a bucket (0 = persistent)
+    int grid;     // blocks per launch: tile count rounded up to a bucket of 4096
     dim3 block;
     int chunk;
     bool row;     // row-form kernels (see row_form_ok)
@@ -703,7 +703,7 @@ int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t ma
     b->slot.assign(capacity, nullptr);
     b->doms.assign(capacity, mplb::BatchDom{});
     b->ntiles_host = 0;
-    b->grid = 0;
+    b->grid = 4096;  // one bucket: an empty batch launches blocks that find no tile
     b->block = dim3(64, 4, 1);
     b->chunk = 16;
     b->t = 0;
@@ -846,18 +846,13 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
         HIPCHK(mplb::launch_set_i64(b->d_tbase, b->t, b->stream));
         if (b->chunk > 0 && left >= b->chunk) {
             if (!b->have_graph) {
-                // persistent grid sizes are looked up outside the capture
-                HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row,
-                                               b->fused, b->d_doms, b->d_tiles, b->d_ntiles,
-                                               b->d_tbase, 0, b->block, b->stream, true));
                 hipGraph_t graph = nullptr;
                 HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
                 hipError_t e = hipSuccess;
                 for (int k = 0; k < b->chunk && e == hipSuccess; ++k)
                     e = mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row,
                                                 b->fused, b->d_doms, b->d_tiles, b->d_ntiles,
-                                                b->d_tbase, k, b->block, b->stream, false,
-                                                b->grid);
+                                                b->d_tbase, k, b->block, b->grid, b->stream);
                 // always end the capture, so that a failure leaves the stream usable
                 const hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
                 if (e != hipSuccess || e2 != hipSuccess) {
@@ -877,7 +872,7 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
         } else {
             HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row, b->fused,
                                            b->d_doms, b->d_tiles, b->d_ntiles, b->d_tbase, 0,
-                                           b->block, b->stream, false, b->grid));
+                                           b->block, b->grid, b->stream));
             b->t += 1;
             done += 1;
         }

@@ -107,23 +107,21 @@ struct BatchTile {
     int dom, x0, y0, z0, z1, w;
 };
 
-// One step of every active domain: persistent blocks stride over the tile
-// list (*ntiles entries); the batch step index is *tbase + step_off.
 // True when the row-form kernels apply: block a multiple of 64 wide in x,
 // x periodic, population arrays of fewer than 2^31 elements.
 bool row_form_ok(int dim, const Geom &g, dim3 block);
 // row: every attached domain satisfies row_form_ok with this block.
-// collision: operator code, bit 0 the flow collision, bit 1 the first-order
-// phase-field equilibrium.  fused: one kernel per step over fused tiles (every attached domain
-// satisfies fused_ok_geom); else the phi pass and the update over block
-// tiles.  The blocks stride over the tile list: fixed_grid > 0 launches that
-// many blocks (at least one per tile: hardware scheduling), else a persistent
-// grid sized to the device; prepare_only looks the persistent sizes up
-// without launching (call it before a graph capture).
+// One batch step over the tile list (*ntiles entries), batch step index
+// *tbase + step_off.  collision: operator code, bit 0 the flow collision, bit
+// 1 the first-order phase-field equilibrium (shared by all domains).  fused:
+// one kernel per step over fused tiles (every attached domain satisfies
+// fused_ok_geom); else the phi pass and the update over block tiles (row:
+// every domain takes the row form).  grid blocks stride over the tiles (at
+// least one per tile: hardware scheduling).
 hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool fused,
                              const BatchDom *doms, const BatchTile *tiles, const int *ntiles,
-                             const long long *tbase, int step_off, dim3 block,
-                             hipStream_t stream, bool prepare_only = false, int fixed_grid = 0);
+                             const long long *tbase, int step_off, dim3 block, int grid,
+                             hipStream_t stream);
 hipError_t launch_set_i64(long long *ptr, long long v, hipStream_t stream);
 
 }  // namespace mplb

@@ -9,7 +9,10 @@
 //   k_collide  per cell: isotropic gradient and Laplacian of phi (Sec. 2.2),
 //              closure (density, chemical potential, forces, normal), flow
 //              collision, phase-field collision, post-collision values
-//              stored at the cell (pull streaming: the next step gathers).
+//              stored at the cell (pull streaming: the next step gathers);
+// or one launch, k_fused, that keeps phi in LDS (see "fused step" below).
+// The batched forms (kb_step, kb_fused) run the same per-cell bodies over a
+// tile list of many independent domains.
 //
 // Flow collision.  All cumulant rates other than the viscous ones are unity
 // (Sec. 2.3), so every post-collision cumulant above second order is zero and
@@ -30,9 +33,6 @@
 #include <hip/hip_fp16.h>
 
 #include <type_traits>
-#include <mutex>
-#include <utility>
-#include <vector>
 
 #include "internal.h"
 
@@ -1080,11 +1080,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double *part
 }
 
 // ------------------------------------------------------------------ batches
-// Many independent domains advance in the same two launches.  Persistent
-// blocks stride over a tile list; each tile names its domain, whose geometry,
-// parameters, buffers and active step window are read from the domain table.
-// The per-cell arithmetic is the single-domain path's (phi_cell,
-// collide_cell), so a domain's result does not depend on the batch it is in.
+// Many independent domains advance in the same launches.  Blocks stride over
+// a tile list (one block per tile when the launch has a block per tile); each
+// tile names its domain, whose geometry, parameters, buffers and active step
+// window are read from the domain table.  The per-cell arithmetic is the
+// single-domain path's (phi_cell, collide_cell, fused_tile), so a domain's
+// result does not depend on the batch it is in.
 
 __device__ __forceinline__ Ptrs batch_ptrs(const BatchDom &d, int in, bool have_prev)
 {
@@ -1142,8 +1143,8 @@ __attribute__((amdgpu_waves_per_eu(PHI ? 1 : collide_waves<D, P, COLL>()))) kb_s
     }
 }
 
-// Batched one-launch step: persistent blocks stride over fused tiles (domain,
-// rows y0 .., planes z0 .. z1 - 1), each a fused_tile of its domain.
+// Batched one-launch step: blocks stride over fused tiles (domain, rows
+// y0 .., planes z0 .. z1 - 1), each a fused_tile of its domain.
 template <int D, class P, int COLL>
 __global__ void __launch_bounds__(FUSED_THREADS)
 __attribute__((amdgpu_waves_per_eu(collide_waves<D, P, COLL>())))
@@ -1301,22 +1302,6 @@ hipError_t launch_step_fused(const Ctx &c)
     });
 }
 
-// Blocks of `kernel` resident on the whole device at once: the size of a
-// persistent grid (larger grids would start their surplus blocks only after
-// the first ones have walked their whole share of the tile list).
-template <class K>
-static int resident_blocks(K kernel, int threads)
-{
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-        return 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    return per_cu * prop.multiProcessorCount;
-}
-
 hipError_t launch_init(const Ctx &c, const double *phi, const double *u, const double *pr)
 {
     return dispatch(c, [&]<int D, class P>() {
@@ -1366,30 +1351,13 @@ hipError_t launch_field(const Ctx &c, int field, double *dst)
 
 hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool fused,
                              const BatchDom *doms, const BatchTile *tiles, const int *ntiles,
-                             const long long *tbase, int step_off, dim3 block,
-                             hipStream_t stream, bool prepare_only, int fixed_grid)
+                             const long long *tbase, int step_off, dim3 block, int grid,
+                             hipStream_t stream)
 {
     Ctx c{};
     c.dim = dim;
     c.storage = storage;
-    const int threads = int(block.x * block.y * block.z);
-    // launches kernel k over a persistent grid sized to the device (the size
-    // is looked up once per kernel, outside any graph capture: prepare_only)
-    auto go = [&](auto k, dim3 blk, int nthreads) {
-        static std::vector<std::pair<const void *, int>> cache;
-        static std::mutex mu;
-        int grid = 0;
-        {
-            std::lock_guard<std::mutex> lock(mu);
-            for (auto &e : cache)
-                if (e.first == reinterpret_cast<const void *>(k)) grid = e.second;
-            if (grid == 0) {
-                grid = resident_blocks(k, nthreads);
-                cache.emplace_back(reinterpret_cast<const void *>(k), grid);
-            }
-        }
-        if (prepare_only) return hipSuccess;
-        if (fixed_grid > 0) grid = fixed_grid;
+    auto go = [&](auto k, dim3 blk) {
         hipLaunchKernelGGL(k, dim3(grid), blk, 0, stream, doms, tiles, ntiles, tbase, step_off);
         return hipGetLastError();
     };
@@ -1397,17 +1365,17 @@ hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool
     // phase-field equilibrium), shared by every domain of the batch
     return dispatch(c, [&]<int D, class P>() {
         if constexpr (D == 3) {
-            if (fused && collision == 0) return go(kb_fused<3, P, 0>, dim3(FUSED_THREADS), FUSED_THREADS);
-            if (fused && collision == 2) return go(kb_fused<3, P, 2>, dim3(FUSED_THREADS), FUSED_THREADS);
+            if (fused && collision == 0) return go(kb_fused<3, P, 0>, dim3(FUSED_THREADS));
+            if (fused && collision == 2) return go(kb_fused<3, P, 2>, dim3(FUSED_THREADS));
         }
         if (fused) return hipErrorInvalidValue;
-        hipError_t e = row ? go(kb_step<D, P, 0, true, true>, block, threads)
-                           : go(kb_step<D, P, 0, true, false>, block, threads);
+        hipError_t e = row ? go(kb_step<D, P, 0, true, true>, block)
+                           : go(kb_step<D, P, 0, true, false>, block);
         if (e != hipSuccess) return e;
         return with_coll(collision, [&](auto cc) {
             constexpr int COLL = decltype(cc)::value;
-            return row ? go(kb_step<D, P, COLL, false, true>, block, threads)
-                       : go(kb_step<D, P, COLL, false, false>, block, threads);
+            return row ? go(kb_step<D, P, COLL, false, true>, block)
+                       : go(kb_step<D, P, COLL, false, false>, block);
         });
     });
 }

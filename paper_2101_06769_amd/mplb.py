@@ -285,7 +285,7 @@ class Solver:
 
 class Batch:
     """Many solvers of one dimension and storage format stepped together
-    (persistent launches over a tile list, hipGraph-replayed chunks)."""
+    (launches over a tile list, one block per tile, hipGraph-replayed chunks)."""
 
     def __init__(self, dim, storage="fp32", capacity=64, max_tiles=1 << 20, stream=None,
                  device=None):

@@ -3,7 +3,7 @@
 Requests (a case, its initial fields and a number of steps) arrive over time.
 The continuous-batching server admits them in arrival order while its
 device-memory budget and a batch slot allow. Each admitted state stays
-resident in HBM. All admitted solves advance in the same persistent batched
+resident in HBM. All admitted solves advance in the same batched
 launches (graph-replayed chunks of steps). A request that arrives while
 others run joins at the next step boundary. A finished solve is read back
 (phi, u, p), detached, and its memory returned to the budget.

@@ -1,0 +1,39 @@
+"""Host-side checks of bench.py's contract that need no GPU."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_profiled_traffic_is_tied_to_the_kernel_sources(tmp_path, monkeypatch):
+    # the committed summary matches the tree; a changed source or another
+    # workload gives None
+    t = bench.profiled_traffic("fp32", 512, "k_collide")
+    assert t is None or 3.0e9 < t < 5.0e9
+    assert bench.profiled_traffic("fp16s", 512, "k_collide") is None
+    assert bench.profiled_traffic("fp32", 256, "k_collide") is None
+    fake = tmp_path / "p.md"
+    fake.write_text("x\n```json\n" + json.dumps({"kernel": "k_collide", "sources_sha256": "0" * 64,
+                                                   "traffic_bytes_per_launch": 1}) + "\n```\n")
+    monkeypatch.setitem(bench.TRAFFIC_PROFILES, "k_collide", str(fake))
+    assert bench.profiled_traffic("fp32", 512, "k_collide") is None
+
+
+def test_algorithmic_bytes_follow_the_storage_sizes():
+    # read and write every population once (+ phi for the two-kernel form)
+    assert bench.ALG_BYTES[("fp32", 3)]["collide"] == 27 * 4 * 4 + 4
+    assert bench.ALG_BYTES[("fp32", 3)]["method"] == 27 * 4 * 4 + 8
+    assert bench.ALG_BYTES[("fp32", 3)]["fused"] == 27 * 4 * 4
+    assert bench.ALG_BYTES[("fp64", 3)]["collide"] == 2 * bench.ALG_BYTES[("fp32", 3)]["collide"]
+    assert bench.ALG_BYTES[("fp32", 2)]["method"] == 9 * 4 * 4 + 8

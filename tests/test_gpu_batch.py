@@ -1,5 +1,5 @@
 """GPU tests of the batched path: many independent domains of uneven size and
-parameters advanced together (persistent launches over a tile list, graph
+parameters advanced together (launches over a tile list, graph
 replay).  A domain's result must be bitwise identical alone and in the mix
 (same per-cell arithmetic), for any activity window, and match the oracle on
 the first steps."""
