@@ -44,6 +44,17 @@ ALG_BYTES = {("fp32", 3): {"collide": 436, "phi": 112, "method": 440, "fused": 4
 # (read and written once), which is also what the method must move per step.
 
 
+def nphi_bytes(storage, rows):
+    """Algorithmic bytes per cell of the update that also sums the next phi
+    (k_collide_nphi: the collide bytes plus its partial sums, three per cell
+    and three more for each of the two edge rows of a tile of `rows` rows)
+    and of the merge that adds them (k_phi_merge: the partial sums read,
+    phi written)."""
+    s = 8 if storage == "fp64" else 4
+    part = s * (3 + 6.0 / rows)
+    return ALG_BYTES[(storage, 3)]["collide"] + part, part + s
+
+
 KERNEL_SOURCES = ("kernels.hip", "lattice.hpp", "internal.h")
 TRAFFIC_PROFILES = {
     "k_fused": os.path.join(ROOT, "profiles", "k_fused_rti3d_128x128x512_fp32_hbm_bytes.md"),
@@ -439,6 +450,10 @@ def main():
     ap.add_argument("--fuse", type=int, default=1, choices=[0, 1, 2],
                     help="one-launch step: 0 never (phi pass + update), 1 where it is the "
                          "faster form (default), 2 wherever it applies")
+    ap.add_argument("--phi-partials", type=int, default=1, choices=[0, 1],
+                    help="1: the update sums the next phi from the values it stores and the "
+                         "next step merges the partial sums (default, where it applies); 0: a "
+                         "phi pass over the pulled populations every step")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="rti3d",
                     choices=["rti3d", "batch", "serve", "splash", "rti2d_convergence", "stability",
@@ -501,6 +516,7 @@ def main():
     N = case.ncells
     s = mplb.Solver(case.params, storage=args.storage)
     s.set_fused(args.fuse)
+    s.set_phi_partials(args.phi_partials)
     s.init(case.phi, case.u, case.p)
     s.step(args.warmup)
     torch.cuda.synchronize()
@@ -519,8 +535,14 @@ def main():
     m0 = float(case.phi.sum())
     ab = ALG_BYTES[(args.storage, 3)]
     fused = s.uses_fused()
-    kernel = "k_fused" if fused else "k_collide"
-    kbytes = ab["fused"] if fused else ab["collide"]
+    rows = s.phi_partial_rows()
+    if fused:
+        kernel, kbytes, phi_kernel = "k_fused", ab["fused"], None
+    elif rows:
+        kernel, phi_kernel = "k_collide_nphi", "k_phi_merge"
+        kbytes = nphi_bytes(args.storage, rows)[0]
+    else:
+        kernel, kbytes, phi_kernel = "k_collide", ab["collide"], "k_phi"
     method_bytes = ab["fused"] if fused else ab["method"]
     t_col = ms_col / args.steps / 1e3
     achieved = kbytes * N / t_col / 1e9
@@ -547,7 +569,8 @@ def main():
                      "traffic": profiled_traffic(args.storage, args.nz, kernel),
                      "kernel": kernel, "alg_bytes_per_cell": kbytes,
                      "avg_launch_us": round(t_col * 1e6, 2),
-                     "phi_pass_avg_launch_us": None if fused else round(ms_phi / args.steps * 1e3, 2)},
+                     "phi_stage_kernel": phi_kernel,
+                     "phi_stage_avg_launch_us": None if fused else round(ms_phi / args.steps * 1e3, 2)},
         "method_alg_GBs": round(method_bytes * N * args.steps / (ms / 1e3) / 1e9, 1),
         "method_frac": round(method_bytes * N * args.steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "phase_mass_rel_drift": abs(red[0] - m0) / m0,

@@ -197,6 +197,26 @@ int mplb_set_fused(mplb_solver *s, int32_t mode);
  * error. */
 int mplb_uses_fused(const mplb_solver *s);
 
+/* Next order parameter from partial sums (Sec. 2.2: phi at a cell is the
+ * zeroth moment of the populations pulled there).  On 3-D lattices periodic
+ * in x with nx a multiple of 64 up to 256, y and z periodic or walls, and
+ * plain phase-field storage (FP64, FP32, FP16S), the update kernel works on
+ * tiles of whole rows (as many rows as 512 threads, 256 with FP64, allow,
+ * dividing ny), sums each cell's stored phase-field values towards the cells
+ * they stream to while it holds them, and the next step merges a few partial
+ * sums per cell instead of re-reading all Q pulled values.  The sums run in
+ * another order than the pull sum, so results agree with mode 0 to
+ * round-off, not bit for bit (they do not depend on the block shape set by
+ * mplb_set_block).  The first step after mplb_init, mplb_set_populations, a
+ * batch run or a step in mode 0 uses the pull sum.  mode 0: never; 1
+ * (default): wherever it applies (not with the one-launch step).  Errors:
+ * EINVAL. */
+int mplb_set_phi_partials(mplb_solver *s, int32_t mode);
+
+/* Rows per tile (>= 1) if the next update of this solver writes partial
+ * sums of phi, 0 if not; <0 on error. */
+int mplb_uses_phi_partials(const mplb_solver *s);
+
 /* Autotuner: time candidate block shapes for the step kernels (each over
  * `steps` steps after two warm-up steps, device time from HIP events), select
  * the fastest, and write it to best[3].  The solver is advanced by the timed

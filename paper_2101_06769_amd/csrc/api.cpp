@@ -8,6 +8,9 @@
 //                 host transfers
 //   phi           order parameter of the current time level, [np]
 //   fp, fr, gp    per-cell shift/scale of FP16-shifted sets, two of each
+//   phiu          (phi u) of two steps (first-order phase-field equilibrium)
+//   npart, nedge  partial sums of the next phi (lattices the summing update
+//                 kernel can take; edge sized for tiles of one row)
 //   partials      reduction partial sums, result
 #include <hip/hip_runtime.h>
 
@@ -46,7 +49,7 @@ struct Layout {
     int Q;
     long long N, np;
     size_t sF, sG, sT;
-    size_t F[2], G[2], phi, fp[2], fr[2], gp[2], phiu[2], partials, result, total;
+    size_t F[2], G[2], phi, fp[2], fr[2], gp[2], phiu[2], npart, nedge, partials, result, total;
     size_t staging_bytes;
 };
 
@@ -78,6 +81,15 @@ bool validate(const mplb_params *p, std::string &why)
         return why = "unknown collision operator", false;
     if (p->cac_edf != 0 && p->cac_edf != 1) return why = "cac_edf must be 0 or 1", false;
     return true;
+}
+
+// Lattices whose update kernel can sum the next phi (see mplb::nphi_ok; the
+// block shape is checked at each step).
+bool nphi_geom(const mplb_params *p)
+{
+    auto per_or_wall = [](int b) { return b == MPLB_BC_PERIODIC || b == MPLB_BC_WALL; };
+    return p->dim == 3 && p->storage != MPLB_STORE_FP16S_ALL && p->bc[0] == MPLB_BC_PERIODIC &&
+           per_or_wall(p->bc[1]) && per_or_wall(p->bc[2]) && p->n[0] % 64 == 0 && p->n[0] <= 256;
 }
 
 Layout make_layout(const mplb_params *p)
@@ -123,6 +135,13 @@ Layout make_layout(const mplb_params *p)
             L.phiu[k] = off;
             off += up(3 * L.np * L.sT, ALIGN);
         }
+    }
+    L.npart = L.nedge = 0;
+    if (nphi_geom(p)) {
+        L.npart = off;
+        off += up(3 * L.np * L.sT, ALIGN);
+        L.nedge = off;
+        off += up(6 * L.N * L.sT, ALIGN);  // enough for tiles of one row
     }
     L.partials = off;
     off += up(RED_PARTIALS * 8 * sizeof(double), ALIGN);
@@ -185,6 +204,8 @@ struct mplb_solver {
     bool attached;
     bool hist;  // (phi u) of the previous step is stored (first-order phase-field equilibrium)
     int fuse;  // one-launch step: 0 never, 1 where faster (FP16 formats), 2 where it applies
+    int nphi;  // update kernel that sums the next phi: 0 never, 1 where it applies
+    bool nphi_valid;  // the last update wrote partial sums of the current phi
     dim3 block;
     mplb::PhysD ph;
 
@@ -192,6 +213,28 @@ struct mplb_solver {
     bool use_fused(const mplb::Ctx &c) const
     {
         return fuse != 0 && mplb::fused_ok(c) && (fuse == 2 || mplb::fused_preferred(prm.storage));
+    }
+    bool use_nphi(const mplb::Ctx &c) const
+    {
+        return nphi != 0 && L.npart != 0 && !use_fused(c) && mplb::nphi_ok(c);
+    }
+    mplb::NextPhi next_phi() const
+    {
+        return mplb::NextPhi{at(L.npart), at(L.nedge),
+                             mplb::nphi_rows(prm.n[0], prm.n[1], prm.storage)};
+    }
+    // The phi stage of a step: merge the partial sums the previous update
+    // wrote, or sum the pulled populations.
+    hipError_t launch_phi_stage(const mplb::Ctx &c) const
+    {
+        if (use_nphi(c) && nphi_valid) return mplb::launch_phi_merge(c, next_phi());
+        return mplb::launch_phi(c);
+    }
+    // The update stage; records whether it left partial sums for the next step.
+    hipError_t launch_update_stage(const mplb::Ctx &c)
+    {
+        nphi_valid = use_nphi(c);
+        return nphi_valid ? mplb::launch_collide_nphi(c, next_phi()) : mplb::launch_collide(c);
     }
     void *F(int k) const { return base + L.F[k]; }
     void *G(int k) const { return base + L.G[k]; }
@@ -282,6 +325,8 @@ int mplb_create(const mplb_params *p, void *dev_arena, size_t arena_bytes, void 
     s->attached = false;
     s->block = default_block(p);
     s->fuse = 1;
+    s->nphi = 1;
+    s->nphi_valid = false;
     s->ph = make_phys(p);
     *out = s;
     return MPLB_OK;
@@ -346,6 +391,20 @@ int mplb_uses_fused(const mplb_solver *s)
     return s->use_fused(s->ctx(s->cur)) ? 1 : 0;
 }
 
+int mplb_set_phi_partials(mplb_solver *s, int32_t mode)
+{
+    if (!s) return fail(MPLB_EINVAL, "solver is NULL");
+    if (mode != 0 && mode != 1) return fail(MPLB_EINVAL, "mode must be 0 or 1");
+    s->nphi = mode;
+    return MPLB_OK;
+}
+
+int mplb_uses_phi_partials(const mplb_solver *s)
+{
+    if (!s) return fail(MPLB_EINVAL, "solver is NULL");
+    return s->use_nphi(s->ctx(s->cur)) ? s->next_phi().by : 0;
+}
+
 int mplb_set_block(mplb_solver *s, int32_t bx, int32_t by, int32_t bz)
 {
     if (!s) return fail(MPLB_EINVAL, "solver is NULL");
@@ -382,6 +441,7 @@ int mplb_init(mplb_solver *s, const double *phi, const double *u, const double *
     s->steps = 0;
     s->ready = true;
     s->hist = false;
+    s->nphi_valid = false;
     return MPLB_OK;
 }
 
@@ -394,10 +454,11 @@ int mplb_step(mplb_solver *s, int64_t nsteps)
     for (int64_t i = 0; i < nsteps; ++i) {
         const mplb::Ctx c = s->ctx(s->cur);
         if (s->use_fused(c)) {
+            s->nphi_valid = false;
             HIPCHK(mplb::launch_step_fused(c));
         } else {
-            HIPCHK(mplb::launch_phi(c));
-            HIPCHK(mplb::launch_collide(c));
+            HIPCHK(s->launch_phi_stage(c));
+            HIPCHK(s->launch_update_stage(c));
         }
         s->cur ^= 1;
         s->steps++;
@@ -422,9 +483,10 @@ int mplb_step_timed(mplb_solver *s, int64_t nsteps, double *ms_phi, double *ms_c
         for (int i = 0; i < k && e == hipSuccess; ++i) {
             const mplb::Ctx c = s->ctx(s->cur);
             const bool fused = s->use_fused(c);
-            e = fused ? hipSuccess : mplb::launch_phi(c);
+            if (fused) s->nphi_valid = false;
+            e = fused ? hipSuccess : s->launch_phi_stage(c);
             if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 1], s->stream);
-            if (e == hipSuccess) e = fused ? mplb::launch_step_fused(c) : mplb::launch_collide(c);
+            if (e == hipSuccess) e = fused ? mplb::launch_step_fused(c) : s->launch_update_stage(c);
             if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 2], s->stream);
             s->cur ^= 1;
             s->steps++;
@@ -533,6 +595,7 @@ int mplb_set_populations(mplb_solver *s, int32_t which, const double *host_in)
     s->ready = true;
     s->steps = 0;
     s->hist = false;
+    s->nphi_valid = false;
     return MPLB_OK;
 }
 
@@ -887,7 +950,10 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
         const long long adv = hi > lo ? hi - lo : 0;
         s->steps += adv;
         s->cur = int((s->cur + adv) & 1);
-        if (adv > 0) s->hist = true;
+        if (adv > 0) {
+            s->hist = true;
+            s->nphi_valid = false;  // the batched update leaves no partial sums
+        }
     }
     return MPLB_OK;
 }

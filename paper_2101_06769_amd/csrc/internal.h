@@ -59,6 +59,25 @@ struct Ctx {
 
 hipError_t launch_phi(const Ctx &c);
 hipError_t launch_collide(const Ctx &c);
+// Partial sums of the next order parameter, written by launch_collide_nphi
+// for launch_phi_merge of the following step: part [3][np], edge
+// [2][3][ny / by][nz][nx] in the arithmetic type; by = tile rows,
+// nphi_rows(nx, ny, storage format).
+struct NextPhi {
+    void *part;
+    void *edge;
+    int by;
+};
+// The update kernel that also sums the next order parameter from the values
+// it stores, tile by tile (3-D, x periodic with nx a multiple of 64 up to
+// 256, y and z periodic or walls, plain phase-field storage); nphi_ok tells
+// whether it applies.  Its tiles are whole rows by nphi_rows rows, whatever
+// the block shape of the other kernels.
+bool nphi_ok(const Ctx &c);
+int nphi_rows(int nx, int ny, int storage);
+hipError_t launch_collide_nphi(const Ctx &c, const NextPhi &q);
+// phi of the current level from the partial sums of the previous update.
+hipError_t launch_phi_merge(const Ctx &c, const NextPhi &q);
 // One-launch step (phi into LDS, then the collision) for 3-D cumulant
 // lattices periodic in x with nx <= 256 and arrays of fewer than 2^31
 // elements; fused_ok tells whether it applies.  It does not write the phi

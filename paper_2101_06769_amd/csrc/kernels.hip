@@ -504,10 +504,13 @@ __global__ void __launch_bounds__(256) k_phi(Geom g, Ptrs p);
 // The fused update of one cell: stencil, closure, flow collision, phase-field
 // collision; post-collision values stored at the cell.  COLL bit 0: flow
 // collision (0 cumulant, 1 single relaxation time); bit 1: first-order
-// phase-field equilibrium with the correction term.
-template <int D, class P, int COLL, class NB>
+// phase-field equilibrium with the correction term.  KEEP: the stored
+// phase-field values are also written to keep[a * kstride] (LDS), for the
+// partial sums of the next order parameter.
+template <int D, class P, int COLL, class NB, bool KEEP = false>
 __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
-                                             const Phys<typename P::T> &ph, const Ptrs &p)
+                                             const Phys<typename P::T> &ph, const Ptrs &p,
+                                             typename P::T *keep = nullptr, int kstride = 0)
 {
     using T = typename P::T;
     constexpr int Q = Lat<D>::Q;
@@ -639,6 +642,7 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
             gsum += gout;
             __builtin_nontemporal_store(typename P::G::raw(gout),
                 lane_ptr(static_cast<typename P::G::raw *>(p.Gout), (long long)a * g.np + row, xl));
+            if constexpr (KEEP) keep[a * kstride] = gout;
         }
     };
     auto cac = [&](auto first_order) {
@@ -683,8 +687,10 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
             const T g0 = E1 ? weight<D, T>(a0) : weight<D, T>(a0) * gbase;
             gemit(a0, v0 + (c.phi * g0 - v0) * ph.inv_tpb);
         } else {
-            __builtin_nontemporal_store(typename P::G::raw(c.phi - gsum),
+            const T g0 = c.phi - gsum;
+            __builtin_nontemporal_store(typename P::G::raw(g0),
                 lane_ptr(static_cast<typename P::G::raw *>(p.Gout), (long long)(Q / 2) * g.np + row, xl));
+            if constexpr (KEEP) keep[(Q / 2) * kstride] = g0;
         }
     };
     cac(std::integral_constant<bool, (COLL & 2) != 0>{});
@@ -736,6 +742,173 @@ k_collide(Geom g, Phys<typename P::T> ph, Ptrs p)
                      y, z);
     if (x >= g.nx || y >= g.ny || z >= g.nz) return;
     collide_cell<D, P, COLL, NbOf<ROW>>(g, ph, p, x, y, z);
+}
+
+// ------------------------------------------------------- next order parameter
+// phi^{n+1}(x) is the zeroth moment of the populations pulled at x (Sec. 2.2),
+// sum_a g*_a(x - c_a) under periodic wrap, with bounced-back values where the
+// source lies beyond a wall.  Instead of a separate pass that re-reads all Q
+// post-collision values of every cell, the update kernel sums them where they
+// are produced.  A block updates whole x-rows (block.x = nx, x periodic) of
+// by = block.y rows of one plane z (by from nphi_rows), keeps its
+// post-collision g* in LDS ([PAD + row][a][x]; with 4-byte values one unused
+// row in front, so that every read is a per-lane base plus a constant, which
+// FP64 tiles cannot afford: two of them would no longer fit a CU) and, after
+// a barrier, sums for every destination cell the values it received from
+// this tile, split by the source plane:
+//   part[oz][d]     (oz = -1, 0, 1; d in the tile's rows of plane z + oz): the
+//                   values that left this tile's plane z towards d, plus, for
+//                   oz = 0, the cell's own values that bounced back from a wall
+//                   in y or z;
+//   edge[0][oz][t]  the values from the last row of tile t - 1 to the first
+//                   row of tile t; edge[1][oz][t] from the first row of tile
+//                   t + 1 to the last row of tile t ([2][3][ny / by][nz][nx];
+//                   tiles wrap in periodic y, end at walls).
+// k_phi_merge adds the pieces of each cell in a fixed order.  Lattices: 3-D,
+// x periodic with nx a multiple of 64 up to 256, y and z periodic or walls;
+// phase-field populations in plain storage.
+
+template <typename T>
+__host__ __device__ constexpr int nphi_pad() { return sizeof(T) == 4 ? 1 : 0; }
+
+// Rows per tile: as many as the thread budget allows, dividing ny.  512
+// threads for FP32 (four wavefronts per SIMD, two tiles per CU); 256 for
+// FP64, whose LDS tile would otherwise pass 64 KiB, and for FP16S, whose
+// update holds too many registers for two 512-thread tiles per CU.
+constexpr int NPHI_THREADS = 512;
+static int nphi_threads(int storage) { return storage == ST_FP32 ? NPHI_THREADS : 256; }
+int nphi_rows(int nx, int ny, int storage)
+{
+    const int cap = nphi_threads(storage) / nx;
+    for (int by = cap; by > 1; --by)
+        if (ny % by == 0) return by;
+    return 1;
+}
+__device__ __forceinline__ long long nphi_edge_at(const Geom &g, int ntiles, int kind, int oz, int t,
+                                                  int z, int x)
+{
+    return ((((long long)kind * 3 + oz + 1) * ntiles + t) * g.nz + z) * g.nx + x;
+}
+
+// BX = nx, a compile-time row length so that every LDS offset is an immediate.
+template <class P, int COLL, int BX>
+__global__ void __launch_bounds__(NPHI_THREADS) __attribute__((amdgpu_waves_per_eu(collide_waves<3, P, COLL>())))
+k_collide_nphi(Geom g, Phys<typename P::T> ph, Ptrs p, NextPhi q)
+{
+    using T = typename P::T;
+    extern __shared__ double nphi_lds[];
+    T *lds = reinterpret_cast<T *>(nphi_lds);
+    constexpr int bx = BX, RS = 27 * BX;  // row stride
+    constexpr int PAD = nphi_pad<T>();
+    const int by = q.by;
+    const int x = int(threadIdx.x);
+    const int ty = __builtin_amdgcn_readfirstlane(int(threadIdx.y));
+    const int t = int(blockIdx.y);
+    const int y = __builtin_amdgcn_readfirstlane(t * by + ty);
+    const int z = __builtin_amdgcn_readfirstlane(int(blockIdx.z));
+    const NbRow nb = make_nb(g, x, y, z, (NbRow *)nullptr);
+    collide_body<3, P, COLL, NbRow, true>(nb, g, ph, p, lds + (ty + PAD) * RS + x, bx);
+    __syncthreads();
+
+    // column pointers at LDS row ty: value a of tile row r of source column
+    // x - ox is col[ox + 1][(r - ty + PAD) RS + a bx]
+    const T *col[3] = {lds + ty * RS + nb.xp, lds + ty * RS + x, lds + ty * RS + nb.xm};
+    auto V = [&](int a, int r, int c) { return col[c][(r - ty + PAD) * RS + a * bx]; };
+    T *part = static_cast<T *>(q.part);
+    T *edge = static_cast<T *>(q.edge);
+    const int ntiles = g.ny / by;
+    const bool wy = g.bcy == BC_WALL, wz = g.bcz == BC_WALL;
+    const bool ylo = wy && y == 0, yhi = wy && y == g.ny - 1;
+    const bool zlo = wz && z == 0, zhi = wz && z == g.nz - 1;
+#pragma unroll
+    for (int oz = -1; oz <= 1; ++oz) {
+        int zd = z + oz;
+        if (zd < 0 || zd >= g.nz) {
+            if (wz) continue;  // those values bounced back (oz = 0 below)
+            zd += zd < 0 ? g.nz : -g.nz;
+        }
+        T s = 0;
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy) {
+            const int r = ty - oy;
+            if (r >= 0 && r < by) {
+#pragma unroll
+                for (int ox = -1; ox <= 1; ++ox)
+                    s += V((ox + 1) + 3 * (oy + 1) + 9 * (oz + 1), r, ox + 1);
+            }
+        }
+        if (oz == 0 && (ylo || yhi || zlo || zhi)) {
+#pragma unroll
+            for (int b = 0; b < 27; ++b) {
+                const int by_ = cy_of(b), bz = cz_of<3>(b);
+                if ((ylo && by_ == -1) || (yhi && by_ == 1) || (zlo && bz == -1) || (zhi && bz == 1))
+                    s += V(b, ty, 1);
+            }
+        }
+        *lane_ptr(part, (long long)(oz + 1) * g.np + (zd * g.ny + y) * g.nx, x) = s;
+        if (ty == 0 && (!wy || t > 0)) {
+            T e = 0;
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) e += V((ox + 1) + 9 * (oz + 1), 0, ox + 1);
+            edge[nphi_edge_at(g, ntiles, 1, oz, t > 0 ? t - 1 : ntiles - 1, zd, x)] = e;
+        }
+        if (ty == by - 1 && (!wy || t < ntiles - 1)) {
+            T e = 0;
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) e += V((ox + 1) + 6 + 9 * (oz + 1), by - 1, ox + 1);
+            edge[nphi_edge_at(g, ntiles, 0, oz, t < ntiles - 1 ? t + 1 : 0, zd, x)] = e;
+        }
+    }
+}
+
+// Block (64, 4): each wavefront is 64 cells of one row, so y, z and every
+// index but x are wavefront-uniform; each thread merges MERGE_Z planes, all
+// loads issued before the sums.
+constexpr int MERGE_Z = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_phi_merge(Geom g, Ptrs p, NextPhi q)
+{
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = __builtin_amdgcn_readfirstlane(int(blockIdx.y * 4 + threadIdx.y));
+    const int z0 = int(blockIdx.z) * MERGE_Z;
+    if (y >= g.ny) return;
+    const int by = q.by, ntiles = g.ny / by;
+    const int t = y / by, r = y - t * by;
+    const bool wy = g.bcy == BC_WALL, wz = g.bcz == BC_WALL;
+    const bool first = r == 0 && (!wy || t > 0), last = r == by - 1 && (!wy || t < ntiles - 1);
+    const T *__restrict__ part = static_cast<const T *>(q.part);
+    const T *__restrict__ edge = static_cast<const T *>(q.edge);
+    T v[MERGE_Z][3][3];
+#pragma unroll
+    for (int k = 0; k < MERGE_Z; ++k) {
+        const int z = z0 + k;
+#pragma unroll
+        for (int oz = -1; oz <= 1; ++oz) {
+            const int zs = z - oz;
+            const bool ok = z < g.nz && !(wz && (zs < 0 || zs >= g.nz));
+            const long long row = (long long)(z * g.ny + y) * g.nx;
+            v[k][oz + 1][0] = ok ? *lane_ptr(part, (oz + 1) * g.np + row, x) : T(0);
+            v[k][oz + 1][1] = ok && first ? *lane_ptr(edge, nphi_edge_at(g, ntiles, 0, oz, t, z, 0), x) : T(0);
+            v[k][oz + 1][2] = ok && last ? *lane_ptr(edge, nphi_edge_at(g, ntiles, 1, oz, t, z, 0), x) : T(0);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < MERGE_Z; ++k) {
+        const int z = z0 + k;
+        if (z >= g.nz) break;
+        T s = 0;
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz) {
+            // the same terms, in the same order, as when each is present
+            const int zs = z - (oz - 1);
+            if (wz && (zs < 0 || zs >= g.nz)) continue;
+            s += v[k][oz][0];
+            if (first) s += v[k][oz][1];
+            if (last) s += v[k][oz][2];
+        }
+        *lane_ptr(static_cast<T *>(p.phi), (long long)(z * g.ny + y) * g.nx, x) = s;
+    }
 }
 
 // ------------------------------------------------------------- fused step
@@ -1250,6 +1423,61 @@ hipError_t launch_collide(const Ctx &c)
                                    c.stream, c.g, to_phys<T>(c.ph), c.p);
             return hipGetLastError();
         });
+    });
+}
+
+bool nphi_ok(const Ctx &c)
+{
+    const Geom &g = c.g;
+    return c.dim == 3 && (c.storage == ST_FP64 || c.storage == ST_FP32 || c.storage == ST_FP16S) &&
+           g.bcx == BC_PER && (g.bcy == BC_PER || g.bcy == BC_WALL) &&
+           (g.bcz == BC_PER || g.bcz == BC_WALL) && g.nx % 64 == 0 && g.nx <= 256 &&
+           27 * g.np < (1ll << 31);
+}
+
+static bool nphi_tile_ok(const Ctx &c, const NextPhi &q)
+{
+    return nphi_ok(c) && q.by == nphi_rows(c.g.nx, c.g.ny, c.storage);
+}
+
+hipError_t launch_collide_nphi(const Ctx &c, const NextPhi &q)
+{
+    if (!nphi_tile_ok(c, q)) return hipErrorInvalidValue;
+    return dispatch(c, [&]<int D, class P>() {
+        using T = typename P::T;
+        if constexpr (D != 3 || P::G::shifted) {
+            return hipErrorInvalidValue;
+        } else {
+            const dim3 block(c.g.nx, q.by, 1);
+            const dim3 grid(1, c.g.ny / q.by, c.g.nz);
+            const size_t lds = size_t(27) * block.x * (block.y + nphi_pad<T>()) * sizeof(T);
+            return with_coll(coll_code(c.ph), [&](auto cc) {
+                constexpr int COLL = decltype(cc)::value;
+                auto go = [&](auto kernel) {
+                    hipLaunchKernelGGL(kernel, grid, block, lds, c.stream, c.g, to_phys<T>(c.ph),
+                                       c.p, q);
+                    return hipGetLastError();
+                };
+                switch (c.g.nx) {
+                case 64: return go(k_collide_nphi<P, COLL, 64>);
+                case 128: return go(k_collide_nphi<P, COLL, 128>);
+                case 192: return go(k_collide_nphi<P, COLL, 192>);
+                case 256: return go(k_collide_nphi<P, COLL, 256>);
+                }
+                return hipErrorInvalidValue;
+            });
+        }
+    });
+}
+
+hipError_t launch_phi_merge(const Ctx &c, const NextPhi &q)
+{
+    if (!nphi_tile_ok(c, q)) return hipErrorInvalidValue;
+    const dim3 grid(c.g.nx / 64, (c.g.ny + 3) / 4, (c.g.nz + MERGE_Z - 1) / MERGE_Z);
+    return dispatch(c, [&]<int D, class P>() {
+        hipLaunchKernelGGL((k_phi_merge<typename P::T>), grid, dim3(64, 4, 1), 0, c.stream, c.g,
+                           c.p, q);
+        return hipGetLastError();
     });
 }
 

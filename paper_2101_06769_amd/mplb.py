@@ -85,6 +85,8 @@ def load_library():
     lib.mplb_set_block.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.mplb_set_fused.argtypes = [vp, ctypes.c_int32]
     lib.mplb_uses_fused.argtypes = [vp]
+    lib.mplb_set_phi_partials.argtypes = [vp, ctypes.c_int32]
+    lib.mplb_uses_phi_partials.argtypes = [vp]
     lib.mplb_destroy.argtypes = [vp]
     lib.mplb_destroy.restype = None
     i32p = ctypes.POINTER(ctypes.c_int32)
@@ -265,6 +267,21 @@ class Solver:
         if r < 0:
             check(r)
         return bool(r)
+
+    def set_phi_partials(self, mode=1):
+        """0: phi by the pull sum each step; 1: from the partial sums the
+        previous update wrote, where that applies."""
+        check(self._lib.mplb_set_phi_partials(self.h, int(mode)))
+
+    def uses_phi_partials(self):
+        return self.phi_partial_rows() > 0
+
+    def phi_partial_rows(self):
+        """Tile rows of the update that sums the next phi; 0 if it does not."""
+        r = self._lib.mplb_uses_phi_partials(self.h)
+        if r < 0:
+            check(r)
+        return int(r)
 
     def set_block(self, bx, by, bz=1):
         check(self._lib.mplb_set_block(self.h, int(bx), int(by), int(bz)))
