@@ -6,10 +6,12 @@ conservative Allen-Cahn populations, 128 x 128 x 512 lattice, periodic in x/y,
 no-slip walls in z, Atwood 0.5, Re 1000, W 5, mobility 0.1, interface at
 z = 256 with a two-mode cosine perturbation of amplitude 0.05 * 128, FP32
 storage and arithmetic.  A "step" advances both population sets of every
-cell by one time step (the order-parameter pass plus the fused collision).
+cell by one time step: the order parameter of the current level (merged from
+the partial sums the previous update wrote, or a pass over the pulled
+populations) plus the fused update of every cell.
 
 Prints one JSON line: MLUPS (million lattice-cell updates per second) with a
-roofline entry for the dominant kernel (fused collision, HBM-bound) and the
+roofline entry for the dominant kernel (the fused update, HBM-bound) and the
 FP64 CPU oracle's rate on a bounded sample of the same workload.
 """
 import argparse
@@ -59,6 +61,8 @@ KERNEL_SOURCES = ("kernels.hip", "lattice.hpp", "internal.h")
 TRAFFIC_PROFILES = {
     "k_fused": os.path.join(ROOT, "profiles", "k_fused_rti3d_128x128x512_fp32_hbm_bytes.md"),
     "k_collide": os.path.join(ROOT, "profiles", "k_collide_k_phi_rti3d_128x128x512_fp32_hbm_bytes.md"),
+    "k_collide_nphi": os.path.join(ROOT, "profiles",
+                                   "k_collide_nphi_k_phi_merge_rti3d_128x128x512_fp32_hbm_bytes.md"),
 }
 
 
