@@ -133,19 +133,63 @@ __device__ __forceinline__ T pull(const NbLane &n, const void *base, long long n
 
 // Row form: the y and z rules are wavefront-uniform choices of plane and row
 // read off the wavefront's tables; x wraps per lane.  Offsets are 32-bit
-// element indices (the arrays hold fewer than 2^31 elements).
-template <int D, class S, typename T>
-__device__ __forceinline__ T pull(const NbRow &n, const void *base, long long, int a,
-                                  const float *sh, const float *sc)
+// element indices (the arrays hold fewer than 2^31 elements); the uniform
+// part (plane and row) and the lane part (x) of an address stay apart, so the
+// load is a scalar base plus a 32-bit lane offset (three distinct ones: x,
+// x - 1, x + 1) with no per-load vector address arithmetic.
+// Source of the pulled value of direction a: plane dir, row offset rs (both
+// wavefront-uniform), column xs.
+template <int D>
+__device__ __forceinline__ void row_src(const NbRow &n, int a, int &dir, int &rs, int &xs)
 {
     const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
     const int ky = 1 - cy, kz = 1 - cz;  // table index of y - cy, z - cz
     const unsigned by = cy ? 1u << ky : 0u, bz = cz ? 1u << (3 + kz) : 0u;
     const bool bb = (n.bb & (by | bz)) != 0;
     const int b = a - ((n.sym & by) ? 6 * cy : 0) - ((n.sym & bz) ? 18 * cz : 0);
-    const int dir = bb ? opposite<D>(a) : b;
-    const int rs = bb ? n.row : n.ry[ky] + n.rz[kz];
-    const int xs = (bb || cx == 0) ? n.x : cx > 0 ? n.xm : n.xp;
+    dir = bb ? opposite<D>(a) : b;
+    rs = bb ? n.row : n.ry[ky] + n.rz[kz];
+    xs = (bb || cx == 0) ? n.x : cx > 0 ? n.xm : n.xp;
+}
+
+template <int D, class S, typename T>
+__device__ __forceinline__ T pull(const NbRow &n, const void *base, long long, int a,
+                                  const float *sh, const float *sc)
+{
+    int dir, rs, xs;
+    row_src<D>(n, a, dir, rs, xs);
+    const long long off = dir * n.np + rs;
+    if constexpr (S::shifted) {
+        const float q = __half2float(*lane_ptr(static_cast<const __half *>(base), off, xs));
+        const float w = weight<D, float>(a);
+        const float s0 = *lane_ptr(sh, (long long)rs, xs);
+        return T(w * (s0 + (sc ? *lane_ptr(sc, (long long)rs, xs) : 1.0f) * q));
+    } else {
+        return T(*lane_ptr(static_cast<const typename S::raw *>(base), off, xs));
+    }
+}
+
+// Row form with plane, row and column combined into one 32-bit element index
+// per load: more vector address arithmetic, but no scalar base per load.  For
+// kernels at their register limit (the fused step's 512-thread tiles, the
+// FP16 update that also sums phi), where the scalar bases of the split form
+// spill.
+struct NbRowC : NbRow {
+};
+
+__device__ __forceinline__ NbRowC make_nb(const Geom &g, int x, int y, int z, NbRowC *)
+{
+    NbRowC n;
+    static_cast<NbRow &>(n) = make_nb(g, x, y, z, (NbRow *)nullptr);
+    return n;
+}
+
+template <int D, class S, typename T>
+__device__ __forceinline__ T pull(const NbRowC &n, const void *base, long long, int a,
+                                  const float *sh, const float *sc)
+{
+    int dir, rs, xs;
+    row_src<D>(n, a, dir, rs, xs);
     const unsigned cell = unsigned(rs) + unsigned(xs);
     const unsigned e = unsigned(dir * n.np) + cell;
     if constexpr (S::shifted) {
@@ -171,6 +215,13 @@ __device__ __forceinline__ T phi_at(const NbLane &n, const T *phi, int cx, int c
 
 template <typename T>
 __device__ __forceinline__ T phi_at(const NbRow &n, const T *phi, int cx, int cy, int cz)
+{
+    const int xx = cx == 0 ? n.x : cx > 0 ? n.xp : n.xm;
+    return *lane_ptr(phi, (long long)(n.ry[1 + cy] + n.rz[1 + cz]), xx);
+}
+
+template <typename T>
+__device__ __forceinline__ T phi_at(const NbRowC &n, const T *phi, int cx, int cy, int cz)
 {
     const int xx = cx == 0 ? n.x : cx > 0 ? n.xp : n.xm;
     return phi[unsigned(n.ry[1 + cy] + n.rz[1 + cz]) + unsigned(xx)];
@@ -806,8 +857,10 @@ k_collide_nphi(Geom g, Phys<typename P::T> ph, Ptrs p, NextPhi q)
     const int t = int(blockIdx.y);
     const int y = __builtin_amdgcn_readfirstlane(t * by + ty);
     const int z = __builtin_amdgcn_readfirstlane(int(blockIdx.z));
-    const NbRow nb = make_nb(g, x, y, z, (NbRow *)nullptr);
-    collide_body<3, P, COLL, NbRow, true>(nb, g, ph, p, lds + (ty + PAD) * RS + x, bx);
+    // FP16 flow storage: the combined form (the split one spills its bases)
+    using NB = typename std::conditional<P::F::shifted, NbRowC, NbRow>::type;
+    const NB nb = make_nb(g, x, y, z, (NB *)nullptr);
+    collide_body<3, P, COLL, NB, true>(nb, g, ph, p, lds + (ty + PAD) * RS + x, bx);
     __syncthreads();
 
     // column pointers at LDS row ty: value a of tile row r of source column
@@ -931,7 +984,7 @@ __host__ __device__ constexpr int fused_bx(int nx) { return nx <= 64 ? 64 : nx <
 // the LDS rows of planes z - 1, z, z + 1 (each row `rowlen` long, the cell's
 // own row in the middle of three).
 template <typename T>
-struct NbFused : NbRow {
+struct NbFused : NbRowC {
     const T *pl[3];
     int rowlen;
 };
@@ -975,7 +1028,7 @@ __device__ __forceinline__ void fused_tile(const Geom &g, const Phys<typename P:
         for (int r = ty; r < by + 2; r += by) {
             const int yh = halo_coord(y0 - 1 + r, g.ny, g.bcy);
             if (xin) {
-                const NbRow nb = make_nb(g, x, yh, zh, (NbRow *)nullptr);
+                const NbRowC nb = make_nb(g, x, yh, zh, (NbRowC *)nullptr);
                 T sum = 0;
 #pragma unroll
                 for (int a = 0; a < Q; ++a)
@@ -993,7 +1046,7 @@ __device__ __forceinline__ void fused_tile(const Geom &g, const Phys<typename P:
         const int y = y0 + ty;
         if (xin && y < g.ny) {
             NbFused<T> n;
-            static_cast<NbRow &>(n) = make_nb(g, x, y, z, (NbRow *)nullptr);
+            static_cast<NbRowC &>(n) = make_nb(g, x, y, z, (NbRowC *)nullptr);
             n.pl[0] = sphi + sm * psz + (ty + 1) * bx;
             n.pl[1] = sphi + s0 * psz + (ty + 1) * bx;
             n.pl[2] = sphi + sp * psz + (ty + 1) * bx;
