@@ -556,12 +556,17 @@ __global__ void __launch_bounds__(256) k_phi(Geom g, Ptrs p);
 // collision; post-collision values stored at the cell.  COLL bit 0: flow
 // collision (0 cumulant, 1 single relaxation time); bit 1: first-order
 // phase-field equilibrium with the correction term.  KEEP: the stored
-// phase-field values are also written to keep[a * kstride] (LDS), for the
+// phase-field values are also written to keep[nphi_slot(a) * kstride] (LDS),
+// the rest direction's to *keep_rest, for the
 // partial sums of the next order parameter.
+// LDS slot of a moving D3Q27 direction (the rest direction, 13, has none).
+__host__ __device__ constexpr int nphi_slot(int a) { return a < 13 ? a : a - 1; }
+
 template <int D, class P, int COLL, class NB, bool KEEP = false>
 __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
                                              const Phys<typename P::T> &ph, const Ptrs &p,
-                                             typename P::T *keep = nullptr, int kstride = 0)
+                                             typename P::T *keep = nullptr, int kstride = 0,
+                                             typename P::T *keep_rest = nullptr)
 {
     using T = typename P::T;
     constexpr int Q = Lat<D>::Q;
@@ -693,7 +698,7 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
             gsum += gout;
             __builtin_nontemporal_store(typename P::G::raw(gout),
                 lane_ptr(static_cast<typename P::G::raw *>(p.Gout), (long long)a * g.np + row, xl));
-            if constexpr (KEEP) keep[a * kstride] = gout;
+            if constexpr (KEEP) keep[nphi_slot(a) * kstride] = gout;
         }
     };
     auto cac = [&](auto first_order) {
@@ -741,7 +746,7 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
             const T g0 = c.phi - gsum;
             __builtin_nontemporal_store(typename P::G::raw(g0),
                 lane_ptr(static_cast<typename P::G::raw *>(p.Gout), (long long)(Q / 2) * g.np + row, xl));
-            if constexpr (KEEP) keep[(Q / 2) * kstride] = g0;
+            if constexpr (KEEP) *keep_rest = g0;
         }
     };
     cac(std::integral_constant<bool, (COLL & 2) != 0>{});
@@ -801,12 +806,11 @@ k_collide(Geom g, Phys<typename P::T> ph, Ptrs p)
 // source lies beyond a wall.  Instead of a separate pass that re-reads all Q
 // post-collision values of every cell, the update kernel sums them where they
 // are produced.  A block updates whole x-rows (block.x = nx, x periodic) of
-// by = block.y rows of one plane z (by from nphi_rows), keeps its
-// post-collision g* in LDS ([PAD + row][a][x]; with 4-byte values one unused
-// row in front, so that every read is a per-lane base plus a constant, which
-// FP64 tiles cannot afford: two of them would no longer fit a CU) and, after
-// a barrier, sums for every destination cell the values it received from
-// this tile, split by the source plane:
+// by = block.y rows of one plane z (by from nphi_rows), keeps its 26 moving
+// post-collision g* in LDS ([row][slot][x], 53 KB for 512 FP32 or 256 FP64
+// threads: three tiles per CU) and the rest value in a register, and after a
+// barrier sums for every destination cell the values it received from this
+// tile, split by the source plane:
 //   part[oz][d]     (oz = -1, 0, 1; d in the tile's rows of plane z + oz): the
 //                   values that left this tile's plane z towards d, plus, for
 //                   oz = 0, the cell's own values that bounced back from a wall
@@ -818,9 +822,6 @@ k_collide(Geom g, Phys<typename P::T> ph, Ptrs p)
 // k_phi_merge adds the pieces of each cell in a fixed order.  Lattices: 3-D,
 // x periodic with nx a multiple of 64 up to 256, y and z periodic or walls;
 // phase-field populations in plain storage.
-
-template <typename T>
-__host__ __device__ constexpr int nphi_pad() { return sizeof(T) == 4 ? 1 : 0; }
 
 // Rows per tile: as many as the thread budget allows, dividing ny.  512
 // threads for FP32 (four wavefronts per SIMD, two tiles per CU); 256 for
@@ -841,32 +842,22 @@ __device__ __forceinline__ long long nphi_edge_at(const Geom &g, int ntiles, int
     return ((((long long)kind * 3 + oz + 1) * ntiles + t) * g.nz + z) * g.nx + x;
 }
 
-// BX = nx, a compile-time row length so that every LDS offset is an immediate.
-template <class P, int COLL, int BX>
-__global__ void __launch_bounds__(NPHI_THREADS) __attribute__((amdgpu_waves_per_eu(collide_waves<3, P, COLL>())))
-k_collide_nphi(Geom g, Phys<typename P::T> ph, Ptrs p, NextPhi q)
+// The sums of k_collide_nphi after its barrier, for the thread's cell as
+// destination (row ty of the tile, planes z - 1 .. z + 1) and, in the first
+// and last tile rows, for the neighbouring tiles' edge rows.
+template <class P, int BX, int B>
+__device__ __forceinline__ void nphi_gather(const Geom &g, const NextPhi &q,
+                                            const typename P::T *lds, typename P::T rest, int x,
+                                            int xm, int xp, int ty, int y, int z)
 {
     using T = typename P::T;
-    extern __shared__ double nphi_lds[];
-    T *lds = reinterpret_cast<T *>(nphi_lds);
-    constexpr int bx = BX, RS = 27 * BX;  // row stride
-    constexpr int PAD = nphi_pad<T>();
-    const int by = q.by;
-    const int x = int(threadIdx.x);
-    const int ty = __builtin_amdgcn_readfirstlane(int(threadIdx.y));
-    const int t = int(blockIdx.y);
-    const int y = __builtin_amdgcn_readfirstlane(t * by + ty);
-    const int z = __builtin_amdgcn_readfirstlane(int(blockIdx.z));
-    // FP16 flow storage: the combined form (the split one spills its bases)
-    using NB = typename std::conditional<P::F::shifted, NbRowC, NbRow>::type;
-    const NB nb = make_nb(g, x, y, z, (NB *)nullptr);
-    collide_body<3, P, COLL, NB, true>(nb, g, ph, p, lds + (ty + PAD) * RS + x, bx);
-    __syncthreads();
-
-    // column pointers at LDS row ty: value a of tile row r of source column
-    // x - ox is col[ox + 1][(r - ty + PAD) RS + a bx]
-    const T *col[3] = {lds + ty * RS + nb.xp, lds + ty * RS + x, lds + ty * RS + nb.xm};
-    auto V = [&](int a, int r, int c) { return col[c][(r - ty + PAD) * RS + a * bx]; };
+    constexpr int bx = BX, RS = 26 * BX;
+    const int by = q.by, t = int(blockIdx.y);
+    // value a of tile row r, source column x - ox: col[ox + 1][(r - ty + B) RS + slot(a) bx]
+    const T *col[3] = {lds + (ty - B) * RS + xp, lds + (ty - B) * RS + x, lds + (ty - B) * RS + xm};
+    auto V = [&](int a, int r, int c) {
+        return a == 13 ? rest : col[c][(r - ty + B) * RS + nphi_slot(a) * bx];
+    };
     T *part = static_cast<T *>(q.part);
     T *edge = static_cast<T *>(q.edge);
     const int ntiles = g.ny / by;
@@ -912,6 +903,37 @@ k_collide_nphi(Geom g, Phys<typename P::T> ph, Ptrs p, NextPhi q)
             edge[nphi_edge_at(g, ntiles, 0, oz, t < ntiles - 1 ? t + 1 : 0, zd, x)] = e;
         }
     }
+}
+
+
+// BX = nx, a compile-time row length so that every LDS offset is an immediate.
+template <class P, int COLL, int BX>
+__global__ void __launch_bounds__(NPHI_THREADS) __attribute__((amdgpu_waves_per_eu(collide_waves<3, P, COLL>())))
+k_collide_nphi(Geom g, Phys<typename P::T> ph, Ptrs p, NextPhi q)
+{
+    using T = typename P::T;
+    extern __shared__ double nphi_lds[];
+    T *lds = reinterpret_cast<T *>(nphi_lds);
+    constexpr int RS = 26 * BX;  // row stride
+    const int by = q.by;
+    const int x = int(threadIdx.x);
+    const int ty = __builtin_amdgcn_readfirstlane(int(threadIdx.y));
+    const int t = int(blockIdx.y);
+    const int y = __builtin_amdgcn_readfirstlane(t * by + ty);
+    const int z = __builtin_amdgcn_readfirstlane(int(blockIdx.z));
+    // FP16 flow storage: the combined form (the split one spills its bases)
+    using NB = typename std::conditional<P::F::shifted, NbRowC, NbRow>::type;
+    const NB nb = make_nb(g, x, y, z, (NB *)nullptr);
+    T rest;
+    collide_body<3, P, COLL, NB, true>(nb, g, ph, p, lds + ty * RS + x, BX, &rest);
+    __syncthreads();
+    // rows ty - 1 .. ty + 1 are read from a base at row ty - B (B = 1, or 0 in
+    // the first tile row, which reads no row above): every LDS offset is a
+    // non-negative constant
+    if (ty == 0)
+        nphi_gather<P, BX, 0>(g, q, lds, rest, x, nb.xm, nb.xp, ty, y, z);
+    else
+        nphi_gather<P, BX, 1>(g, q, lds, rest, x, nb.xm, nb.xp, ty, y, z);
 }
 
 // Block (64, 4): each wavefront is 64 cells of one row, so y, z and every
@@ -1503,7 +1525,7 @@ hipError_t launch_collide_nphi(const Ctx &c, const NextPhi &q)
         } else {
             const dim3 block(c.g.nx, q.by, 1);
             const dim3 grid(1, c.g.ny / q.by, c.g.nz);
-            const size_t lds = size_t(27) * block.x * (block.y + nphi_pad<T>()) * sizeof(T);
+            const size_t lds = size_t(26) * block.x * block.y * sizeof(T);
             return with_coll(coll_code(c.ph), [&](auto cc) {
                 constexpr int COLL = decltype(cc)::value;
                 auto go = [&](auto kernel) {
