@@ -207,10 +207,11 @@ int mplb_uses_fused(const mplb_solver *s);
  * sums per cell instead of re-reading all Q pulled values.  The sums run in
  * another order than the pull sum, so results agree with mode 0 to
  * round-off, not bit for bit (they do not depend on the block shape set by
- * mplb_set_block).  The first step after mplb_init, mplb_set_populations, a
- * batch run or a step in mode 0 uses the pull sum.  mode 0: never; 1
- * (default): wherever it applies (not with the one-launch step).  Errors:
- * EINVAL. */
+ * mplb_set_block).  The first step after mplb_init, mplb_set_populations or
+ * a step in mode 0 uses the pull sum.  A batch (mplb_batch_*) steps such a
+ * solver the same way, with the same bits; partial sums carry into and out
+ * of a batch run.  mode 0: never; 1 (default): wherever it applies (not
+ * with the one-launch step).  Errors: EINVAL. */
 int mplb_set_phi_partials(mplb_solver *s, int32_t mode);
 
 /* Rows per tile (>= 1) if the next update of this solver writes partial
@@ -230,11 +231,16 @@ void mplb_destroy(mplb_solver *s);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent solvers of one dimension and storage format
- * advance together, two launches per step (one with the fused step) over a
- * tile list that covers every attached lattice, one block per tile.  Each attached solver has its own parameters, lattice size and
- * activity window; a solver's result is identical whether it is stepped
- * alone or in a batch (same per-cell arithmetic).  Steps are replayed from a
- * captured hipGraph in chunks of `graph_chunk` steps.
+ * advance together over a tile list that covers every attached lattice, one
+ * block per tile: per step a phi launch and an update launch (one launch
+ * with the fused step), plus one launch per row length (64, 128, 192, 256)
+ * for the solvers whose update sums the next phi (mplb_set_phi_partials).
+ * Each attached solver has its own parameters, lattice size and activity
+ * window; a solver's result is identical whether it is stepped alone or in
+ * a batch (same per-cell arithmetic, same step form).  Steps are replayed
+ * from a captured hipGraph in chunks of `graph_chunk` steps.  max_tiles
+ * bounds the tile list: per solver about N / (block threads) block tiles,
+ * plus ny nz / rows tiles where the update sums phi.
  * ------------------------------------------------------------------------- */
 typedef struct mplb_batch mplb_batch;
 

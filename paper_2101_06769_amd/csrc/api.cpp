@@ -615,8 +615,14 @@ struct mplb_batch {
     std::vector<mplb_solver *> slot;
     std::vector<mplb::BatchDom> doms;
     std::vector<mplb::BatchTile> tiles;
-    int ntiles_host;
-    int grid;     // blocks per launch: tile count rounded up to a bucket of 4096
+    // tile list: [0, ntiles_host) block tiles of the domains updated by the
+    // block kernels (phi stage and update); [ntiles_host, ntiles_phi_host)
+    // block tiles of the phi-summing domains (phi stage only); then
+    // ntiles_nphi_host tiles of the phi-summing update
+    int ntiles_host, ntiles_phi_host, ntiles_nphi_host;
+    int counts[10];  // the device tile counters (see launch_batch_step)
+    int grid[6];  // blocks of the phi, update and four phi-summing update launches: tile
+                  // counts rounded up to buckets of 4096 (0 for an empty group)
     dim3 block;
     int chunk;
     bool row;     // row-form kernels (see row_form_ok)
@@ -659,64 +665,117 @@ int upload_tables(mplb_batch *b)
     for (int i = 0; i < b->capacity; ++i)
         if (b->slot[i])
             fused = fused && mplb::fused_ok_geom(b->dim, b->collision & 1, b->doms[i].g);
+    // domains whose update sums the next phi, as their solver's own step
+    // would (not with the one-launch step)
+    for (int i = 0; i < b->capacity; ++i) {
+        mplb_solver *s = b->slot[i];
+        if (!s) continue;
+        mplb::BatchDom &d = b->doms[i];
+        const mplb::Ctx c = s->ctx(s->cur);
+        const int by = (!fused && b->dim == 3 && s->use_nphi(c)) ? s->next_phi().by : 0;
+        if (by != d.nphi_by) {
+            d.nphi_by = by;
+            d.nphi_from = b->t + 1;  // no partial sums of the current phi yet
+        }
+        d.npart = by ? s->at(s->L.npart) : nullptr;
+        d.nedge = by ? s->at(s->L.nedge) : nullptr;
+    }
+    // the tile list: block tiles of the other domains (phi stage and update),
+    // block tiles of the phi-summing domains (phi stage: merge), tiles of the
+    // phi-summing update (whole rows of one plane)
     const int threads = int(b->block.x * b->block.y * b->block.z);
     bool row = true;
-    for (int i = 0; i < b->capacity; ++i) {
-        const mplb_solver *s = b->slot[i];
-        if (!s) continue;
-        const int nx = s->prm.n[0], ny = s->prm.n[1], nz = s->prm.n[2];
-        if (fused) {
-            // whole rows, chunks of 32 planes
-            const int rows = mplb::fused_rows(nx), zc = 32;
-            for (int y0 = 0; y0 < ny; y0 += rows)
-                for (int z0 = 0; z0 < nz; z0 += zc) {
-                    if ((long long)b->tiles.size() >= b->max_tiles)
-                        return fail(MPLB_ENOMEM, "batch tile list is full");
-                    b->tiles.push_back(
-                        mplb::BatchTile{i, 0, y0, z0, z0 + zc < nz ? z0 + zc : nz, 0});
-                }
-            continue;
+    auto push = [&](const mplb::BatchTile &tl) {
+        if ((long long)b->tiles.size() >= b->max_tiles) return false;
+        b->tiles.push_back(tl);
+        return true;
+    };
+    int seg[3] = {0, 0, 0};
+    int wstart[4] = {0, 0, 0, 0}, wcount[4] = {0, 0, 0, 0};  // phi-summing tiles by row length
+    for (int pass = 0; pass < 6; ++pass) {
+        const size_t before = b->tiles.size();
+        for (int i = 0; i < b->capacity; ++i) {
+            const mplb_solver *s = b->slot[i];
+            if (!s) continue;
+            const int nx = s->prm.n[0], ny = s->prm.n[1], nz = s->prm.n[2];
+            const int nby = b->doms[i].nphi_by;
+            if (fused) {
+                if (pass != 0) continue;
+                // whole rows, chunks of 32 planes
+                const int rows = mplb::fused_rows(nx), zc = 32;
+                for (int y0 = 0; y0 < ny; y0 += rows)
+                    for (int z0 = 0; z0 < nz; z0 += zc)
+                        if (!push(mplb::BatchTile{i, 0, y0, z0, z0 + zc < nz ? z0 + zc : nz, 0}))
+                            return fail(MPLB_ENOMEM, "batch tile list is full");
+                continue;
+            }
+            if (pass >= 2) {
+                // one group per row length 64, 128, 192, 256
+                if (!nby || nx != 64 * (pass - 1)) continue;
+                for (int z = 0; z < nz; ++z)
+                    for (int y0 = 0; y0 < ny; y0 += nby)
+                        if (!push(mplb::BatchTile{i, 0, y0, z, z + 1, nx}))
+                            return fail(MPLB_ENOMEM, "batch tile list is full");
+                continue;
+            }
+            if ((pass == 0) != (nby == 0)) continue;
+            // tile width: the domain's row rounded up to a power of two, at
+            // least 64 where the row form can apply (x periodic), at most the
+            // block's width; the rest of the block's threads cover further rows
+            int w = 1;
+            while (w < nx) w <<= 1;
+            const bool xper = b->doms[i].g.bcx == mplb::BC_PER;
+            if (xper && w < 64) w = 64;
+            if (w > int(b->block.x)) w = int(b->block.x);
+            if (w > threads) w = threads;
+            const int rows = threads / w;
+            row = row && mplb::row_form_ok(b->dim, b->doms[i].g, dim3(w, rows, 1));
+            for (int z0 = 0; z0 < nz; ++z0)
+                for (int y0 = 0; y0 < ny; y0 += rows)
+                    for (int x0 = 0; x0 < nx; x0 += w)
+                        if (!push(mplb::BatchTile{i, x0, y0, z0, z0 + 1, w}))
+                            return fail(MPLB_ENOMEM, "batch tile list is full");
         }
-        // tile width: the domain's row rounded up to a power of two, at least
-        // 64 where the row form can apply (x periodic), at most the block's
-        // width; the rest of the block's threads cover further rows
-        int w = 1;
-        while (w < nx) w <<= 1;
-        const bool xper = b->doms[i].g.bcx == mplb::BC_PER;
-        if (xper && w < 64) w = 64;
-        if (w > int(b->block.x)) w = int(b->block.x);
-        if (w > threads) w = threads;
-        const int rows = threads / w;
-        row = row && mplb::row_form_ok(b->dim, b->doms[i].g, dim3(w, rows, 1));
-        for (int z0 = 0; z0 < nz; ++z0)
-            for (int y0 = 0; y0 < ny; y0 += rows)
-                for (int x0 = 0; x0 < nx; x0 += w) {
-                    if ((long long)b->tiles.size() >= b->max_tiles)
-                        return fail(MPLB_ENOMEM, "batch tile list is full");
-                    b->tiles.push_back(mplb::BatchTile{i, x0, y0, z0, z0 + 1, w});
-                }
+        if (pass < 2) {
+            seg[pass] = int(b->tiles.size() - before);
+        } else {
+            wstart[pass - 2] = int(before);
+            wcount[pass - 2] = int(b->tiles.size() - before);
+            seg[2] += wcount[pass - 2];
+        }
     }
     if (fused != b->fused) drop_graph(b);
     b->fused = fused;
-    b->ntiles_host = int(b->tiles.size());
+    b->ntiles_host = seg[0];
+    b->ntiles_phi_host = seg[0] + seg[1];
+    b->ntiles_nphi_host = seg[2];
     {
-        // one block per tile, hardware-scheduled; the launch size moves in
+        // one block per tile, hardware-scheduled; the launch sizes move in
         // buckets of 4096 blocks so that a captured graph survives most
         // attach / detach events (surplus blocks find no tile and exit)
         const int bucket = 4096;
-        const int grid = b->ntiles_host ? (b->ntiles_host + bucket - 1) / bucket * bucket : bucket;
-        if (grid != b->grid) drop_graph(b);
-        b->grid = grid;
+        auto bucketed = [&](int n, int empty) { return n ? (n + bucket - 1) / bucket * bucket : empty; };
+        int grid[6] = {bucketed(b->ntiles_phi_host, bucket), bucketed(b->ntiles_host, bucket)};
+        for (int k = 0; k < 4; ++k) grid[2 + k] = bucketed(wcount[k], 0);
+        for (int k = 0; k < 6; ++k)
+            if (grid[k] != b->grid[k]) drop_graph(b);
+        for (int k = 0; k < 6; ++k) b->grid[k] = grid[k];
     }
     if (row != b->row) drop_graph(b);  // a captured graph holds the other kernel
     b->row = row;
     HIPCHK(hipStreamSynchronize(b->stream));
     HIPCHK(hipMemcpyAsync(b->d_doms, b->doms.data(), sizeof(mplb::BatchDom) * b->capacity,
                           hipMemcpyHostToDevice, b->stream));
-    if (b->ntiles_host)
-        HIPCHK(hipMemcpyAsync(b->d_tiles, b->tiles.data(), sizeof(mplb::BatchTile) * b->ntiles_host,
+    if (!b->tiles.empty())
+        HIPCHK(hipMemcpyAsync(b->d_tiles, b->tiles.data(), sizeof(mplb::BatchTile) * b->tiles.size(),
                               hipMemcpyHostToDevice, b->stream));
-    HIPCHK(hipMemcpyAsync(b->d_ntiles, &b->ntiles_host, sizeof(int), hipMemcpyHostToDevice,
+    b->counts[0] = b->ntiles_host;
+    b->counts[1] = b->ntiles_phi_host;
+    for (int k = 0; k < 4; ++k) {
+        b->counts[2 + 2 * k] = wstart[k];
+        b->counts[3 + 2 * k] = wcount[k];
+    }
+    HIPCHK(hipMemcpyAsync(b->d_ntiles, b->counts, sizeof(b->counts), hipMemcpyHostToDevice,
                           b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     return MPLB_OK;
@@ -765,8 +824,10 @@ int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t ma
     b->d_tbase = reinterpret_cast<long long *>(base + ob);
     b->slot.assign(capacity, nullptr);
     b->doms.assign(capacity, mplb::BatchDom{});
-    b->ntiles_host = 0;
-    b->grid = 4096;  // one bucket: an empty batch launches blocks that find no tile
+    b->ntiles_host = b->ntiles_phi_host = b->ntiles_nphi_host = 0;
+    // one bucket: an empty batch launches blocks that find no tile
+    b->grid[0] = b->grid[1] = 4096;
+    for (int k = 2; k < 6; ++k) b->grid[k] = 0;
     b->block = dim3(64, 4, 1);
     b->chunk = 16;
     b->t = 0;
@@ -859,6 +920,11 @@ int mplb_batch_attach(mplb_batch *b, mplb_solver *s, int64_t nsteps, int32_t *sl
     // the domain's first batch step is b->t: history from there if it has one
     d.hist_from = s->hist ? b->t : b->t + 1;
     d.phi = s->base + s->L.phi;
+    // the phi-summing update: upload_tables sets nphi_by and the pointers; a
+    // solver whose last update left partial sums merges them at its first
+    // batch step, as its own next step would
+    d.nphi_by = (b->dim == 3 && s->use_nphi(s->ctx(s->cur))) ? s->next_phi().by : 0;
+    d.nphi_from = s->nphi_valid ? b->t : b->t + 1;
     // input buffer at batch step t is (t - first) & 1; at t = b->t it is s->cur
     d.first = b->t - s->cur;
     d.last = b->t + nsteps;
@@ -952,7 +1018,8 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
         s->cur = int((s->cur + adv) & 1);
         if (adv > 0) {
             s->hist = true;
-            s->nphi_valid = false;  // the batched update leaves no partial sums
+            // the batched update left partial sums of phi if it summed them
+            s->nphi_valid = b->doms[i].nphi_by > 0;
         }
     }
     return MPLB_OK;

@@ -116,6 +116,12 @@ struct BatchDom {
     void *phiu[2];
     long long first, last;  // active for batch steps first <= t < last
     long long hist_from;    // (phi u) of the previous step valid for t >= hist_from
+    // phi-summing update (see NextPhi): tile rows, 0 if the domain's update
+    // does not sum phi; the partial sums; the phi stage of steps t >=
+    // nphi_from merges them (earlier ones sum the pulled populations)
+    int nphi_by;
+    void *npart, *nedge;
+    long long nphi_from;
 };
 
 // A tile of a batch: domain index, origin cell (x0, y0, z0), end of its
@@ -137,10 +143,19 @@ bool row_form_ok(int dim, const Geom &g, dim3 block);
 // fused_ok_geom); else the phi pass and the update over block tiles (row:
 // every domain takes the row form).  grid blocks stride over the tiles (at
 // least one per tile: hardware scheduling).
+// Tile list: ntiles[0] block tiles of the domains the block kernels update,
+// then block tiles of the phi-summing domains up to ntiles[1] (their phi
+// stage merges partial sums), then the tiles of the phi-summing update
+// (domains with nphi_by > 0: whole rows of one plane), grouped by row length
+// 64, 128, 192, 256: group k starts at ntiles[2 + 2k] and holds ntiles[3 + 2k]
+// tiles.  grid[0], grid[1]: blocks of the phi stage and the update;
+// grid[2 + k]: of group k's update (0: not launched).
 hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool fused,
                              const BatchDom *doms, const BatchTile *tiles, const int *ntiles,
-                             const long long *tbase, int step_off, dim3 block, int grid,
+                             const long long *tbase, int step_off, dim3 block, const int *grid,
                              hipStream_t stream);
+// Threads per block of the phi-summing update for a storage format.
+int nphi_block_threads(int storage);
 hipError_t launch_set_i64(long long *ptr, long long v, hipStream_t stream);
 
 }  // namespace mplb

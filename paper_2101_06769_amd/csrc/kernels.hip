@@ -60,15 +60,47 @@ using P32 = Pol<Plain<float>, Plain<float>, float>;
 using P16 = Pol<Half16, Plain<float>, float>;
 using P16A = Pol<Half16, Half16, float>;
 
-// Element x of the row starting at base + off.  The row offset is kept apart
-// from the 32-bit lane offset so that, when it is wavefront-uniform, the
-// address is a scalar base plus a per-lane byte offset.
+// Element x of the row starting at base + off, in device memory (HBM).  The
+// row offset is kept apart from the 32-bit lane offset so that, when it is
+// wavefront-uniform, the address is a scalar base plus a per-lane byte
+// offset.  The result is a global-address-space pointer: a base read from a
+// table (the batched kernels) is otherwise a generic pointer, accessed with
+// flat instructions that also count against the LDS wait counter.
+// FP16 values (a class type, which cannot be copied through such a pointer)
+// are accessed as their 16-bit patterns.
 template <typename R>
-__device__ __forceinline__ R *lane_ptr(R *base, long long off, int x)
+using gptr = __attribute__((address_space(1))) R *;
+template <typename R>
+struct gelem {
+    using type = R;
+};
+template <>
+struct gelem<__half> {
+    using type = unsigned short;
+};
+template <>
+struct gelem<const __half> {
+    using type = const unsigned short;
+};
+
+template <typename R>
+__device__ __forceinline__ gptr<typename gelem<R>::type> lane_ptr(R *base, long long off, int x)
 {
+    using E = typename gelem<R>::type;
     using B = typename std::conditional<std::is_const<R>::value, const char, char>::type;
-    return reinterpret_cast<R *>(reinterpret_cast<B *>(base + off) +
-                                 (unsigned)x * (unsigned)sizeof(R));
+    const gptr<B> row = (gptr<B>)((gptr<E>)base + off);
+    return (gptr<E>)(row + (unsigned)x * (unsigned)sizeof(R));
+}
+
+// Element i of an array in device memory, read as a global access (see lane_ptr).
+template <typename R>
+__device__ __forceinline__ R gld(const R *base, long long i)
+{
+    return ((gptr<const R>)base)[i];
+}
+__device__ __forceinline__ __half gld(const __half *base, long long i)
+{
+    return __ushort_as_half(((gptr<const unsigned short>)base)[i]);
 }
 
 // Value of direction plane `dir` at `cell`.  Shifted FP16 values decode as
@@ -79,11 +111,11 @@ __device__ __forceinline__ T load_pop(const void *base, long long np, int dir, i
                                       const float *sh, const float *sc)
 {
     if constexpr (S::shifted) {
-        const float q = __half2float(static_cast<const __half *>(base)[(long long)dir * np + cell]);
+        const float q = __half2float(gld(static_cast<const __half *>(base), (long long)dir * np + cell));
         const float w = weight<D, float>(a);
-        return T(w * (sh[cell] + (sc ? sc[cell] : 1.0f) * q));
+        return T(w * (gld(sh, cell) + (sc ? gld(sc, cell) : 1.0f) * q));
     } else {
-        return T(static_cast<const typename S::raw *>(base)[(long long)dir * np + cell]);
+        return T(gld(static_cast<const typename S::raw *>(base), (long long)dir * np + cell));
     }
 }
 
@@ -96,7 +128,7 @@ __device__ __forceinline__ void store_dev(void *base, long long np, int a, int r
     if constexpr (S::shifted) {
         const float w = weight<D, float>(a);
         *lane_ptr(static_cast<__half *>(base), (long long)a * np + row, x) =
-            __float2half(float(dev) / (w * float(scale)));
+            __half_as_ushort(__float2half(float(dev) / (w * float(scale))));
     } else {
         __builtin_nontemporal_store(typename S::raw(dev + weight<D, T>(a) * shift),
                                     lane_ptr(static_cast<typename S::raw *>(base),
@@ -110,7 +142,8 @@ __device__ __forceinline__ T load_at(const void *base, long long plane, int row,
                                      const float *sh, const float *sc)
 {
     if constexpr (S::shifted) {
-        const float q = __half2float(*lane_ptr(static_cast<const __half *>(base), plane + row, x));
+        const float q =
+            __half2float(__ushort_as_half(*lane_ptr(static_cast<const __half *>(base), plane + row, x)));
         const float w = weight<D, float>(a);
         const float s = *lane_ptr(sh, row, x);
         const float r = sc ? *lane_ptr(sc, row, x) : 1.0f;
@@ -160,7 +193,7 @@ __device__ __forceinline__ T pull(const NbRow &n, const void *base, long long, i
     row_src<D>(n, a, dir, rs, xs);
     const long long off = dir * n.np + rs;
     if constexpr (S::shifted) {
-        const float q = __half2float(*lane_ptr(static_cast<const __half *>(base), off, xs));
+        const float q = __half2float(__ushort_as_half(*lane_ptr(static_cast<const __half *>(base), off, xs)));
         const float w = weight<D, float>(a);
         const float s0 = *lane_ptr(sh, (long long)rs, xs);
         return T(w * (s0 + (sc ? *lane_ptr(sc, (long long)rs, xs) : 1.0f) * q));
@@ -210,7 +243,7 @@ __device__ __forceinline__ T phi_at(const NbLane &n, const T *phi, int cx, int c
     const int xx = cx ? stencil_coord(n.x + cx, g.nx, g.bcx) : n.x;
     const int yy = cy ? stencil_coord(n.y + cy, g.ny, g.bcy) : n.y;
     const int zz = cz ? stencil_coord(n.z + cz, g.nz, g.bcz) : n.z;
-    return phi[cell_of(g, xx, yy, zz)];
+    return gld(phi, cell_of(g, xx, yy, zz));
 }
 
 template <typename T>
@@ -842,17 +875,18 @@ __device__ __forceinline__ long long nphi_edge_at(const Geom &g, int ntiles, int
     return ((((long long)kind * 3 + oz + 1) * ntiles + t) * g.nz + z) * g.nx + x;
 }
 
-// The sums of k_collide_nphi after its barrier, for the thread's cell as
-// destination (row ty of the tile, planes z - 1 .. z + 1) and, in the first
-// and last tile rows, for the neighbouring tiles' edge rows.
+// The sums of the phi-summing update after its barrier, for the thread's cell
+// as destination (row ty of tile t, planes z - 1 .. z + 1) and, in the first
+// and last tile rows, for the neighbouring tiles' edge rows.  BX: the row
+// length nx, or 0 for a run-time one (bx_rt).
 template <class P, int BX, int B>
 __device__ __forceinline__ void nphi_gather(const Geom &g, const NextPhi &q,
                                             const typename P::T *lds, typename P::T rest, int x,
-                                            int xm, int xp, int ty, int y, int z)
+                                            int xm, int xp, int t, int ty, int y, int z, int bx_rt)
 {
     using T = typename P::T;
-    constexpr int bx = BX, RS = 26 * BX;
-    const int by = q.by, t = int(blockIdx.y);
+    const int bx = BX ? BX : bx_rt, RS = 26 * bx;
+    const int by = q.by;
     // value a of tile row r, source column x - ox: col[ox + 1][(r - ty + B) RS + slot(a) bx]
     const T *col[3] = {lds + (ty - B) * RS + xp, lds + (ty - B) * RS + x, lds + (ty - B) * RS + xm};
     auto V = [&](int a, int r, int c) {
@@ -894,17 +928,48 @@ __device__ __forceinline__ void nphi_gather(const Geom &g, const NextPhi &q,
             T e = 0;
 #pragma unroll
             for (int ox = -1; ox <= 1; ++ox) e += V((ox + 1) + 9 * (oz + 1), 0, ox + 1);
-            edge[nphi_edge_at(g, ntiles, 1, oz, t > 0 ? t - 1 : ntiles - 1, zd, x)] = e;
+            *lane_ptr(edge, nphi_edge_at(g, ntiles, 1, oz, t > 0 ? t - 1 : ntiles - 1, zd, 0), x) = e;
         }
         if (ty == by - 1 && (!wy || t < ntiles - 1)) {
             T e = 0;
 #pragma unroll
             for (int ox = -1; ox <= 1; ++ox) e += V((ox + 1) + 6 + 9 * (oz + 1), by - 1, ox + 1);
-            edge[nphi_edge_at(g, ntiles, 0, oz, t < ntiles - 1 ? t + 1 : 0, zd, x)] = e;
+            *lane_ptr(edge, nphi_edge_at(g, ntiles, 0, oz, t < ntiles - 1 ? t + 1 : 0, zd, 0), x) = e;
         }
     }
 }
 
+
+// One tile of the phi-summing update: rows t by .. t by + by - 1 of plane z,
+// thread (x, ty).  Every thread of the block calls it (it holds a barrier);
+// threads with active false (rows beyond the tile in a larger block) only
+// take part in the barrier.  BX as for nphi_gather.
+template <class P, int COLL, int BX>
+__device__ __forceinline__ void nphi_tile(const Geom &g, const Phys<typename P::T> &ph,
+                                          const Ptrs &p, const NextPhi &q, typename P::T *lds,
+                                          int bx_rt, int t, int ty, int x, int z, bool active)
+{
+    using T = typename P::T;
+    const int bx = BX ? BX : bx_rt, RS = 26 * bx;
+    const int y = __builtin_amdgcn_readfirstlane(t * q.by + ty);
+    // FP16 flow storage: the combined form (the split one spills its bases)
+    using NB = typename std::conditional<P::F::shifted, NbRowC, NbRow>::type;
+    NB nb;
+    T rest = 0;
+    if (active) {
+        nb = make_nb(g, x, y, z, (NB *)nullptr);
+        collide_body<3, P, COLL, NB, true>(nb, g, ph, p, lds + ty * RS + x, bx, &rest);
+    }
+    __syncthreads();
+    if (!active) return;
+    // rows ty - 1 .. ty + 1 are read from a base at row ty - B (B = 1, or 0 in
+    // the first tile row, which reads no row above): every LDS offset is a
+    // non-negative constant when BX is
+    if (ty == 0)
+        nphi_gather<P, BX, 0>(g, q, lds, rest, x, nb.xm, nb.xp, t, ty, y, z, bx_rt);
+    else
+        nphi_gather<P, BX, 1>(g, q, lds, rest, x, nb.xm, nb.xp, t, ty, y, z, bx_rt);
+}
 
 // BX = nx, a compile-time row length so that every LDS offset is an immediate.
 template <class P, int COLL, int BX>
@@ -913,27 +978,29 @@ k_collide_nphi(Geom g, Phys<typename P::T> ph, Ptrs p, NextPhi q)
 {
     using T = typename P::T;
     extern __shared__ double nphi_lds[];
-    T *lds = reinterpret_cast<T *>(nphi_lds);
-    constexpr int RS = 26 * BX;  // row stride
-    const int by = q.by;
-    const int x = int(threadIdx.x);
-    const int ty = __builtin_amdgcn_readfirstlane(int(threadIdx.y));
-    const int t = int(blockIdx.y);
-    const int y = __builtin_amdgcn_readfirstlane(t * by + ty);
-    const int z = __builtin_amdgcn_readfirstlane(int(blockIdx.z));
-    // FP16 flow storage: the combined form (the split one spills its bases)
-    using NB = typename std::conditional<P::F::shifted, NbRowC, NbRow>::type;
-    const NB nb = make_nb(g, x, y, z, (NB *)nullptr);
-    T rest;
-    collide_body<3, P, COLL, NB, true>(nb, g, ph, p, lds + ty * RS + x, BX, &rest);
-    __syncthreads();
-    // rows ty - 1 .. ty + 1 are read from a base at row ty - B (B = 1, or 0 in
-    // the first tile row, which reads no row above): every LDS offset is a
-    // non-negative constant
-    if (ty == 0)
-        nphi_gather<P, BX, 0>(g, q, lds, rest, x, nb.xm, nb.xp, ty, y, z);
-    else
-        nphi_gather<P, BX, 1>(g, q, lds, rest, x, nb.xm, nb.xp, ty, y, z);
+    nphi_tile<P, COLL, BX>(g, ph, p, q, reinterpret_cast<T *>(nphi_lds), BX, int(blockIdx.y),
+                           __builtin_amdgcn_readfirstlane(int(threadIdx.y)), int(threadIdx.x),
+                           __builtin_amdgcn_readfirstlane(int(blockIdx.z)), true);
+}
+
+// The pieces of one cell's phi in a fixed order: for source planes z + 1, z,
+// z - 1 (oz = -1, 0, 1) the tile's own sum, then the sums from the tiles
+// below and above where the cell lies on a tile's first or last row.
+template <typename T>
+__device__ __forceinline__ T nphi_merge_sum(const Geom &g, const T (&v)[3][3], int z, bool first,
+                                            bool last)
+{
+    const bool wz = g.bcz == BC_WALL;
+    T s = 0;
+#pragma unroll
+    for (int oz = 0; oz < 3; ++oz) {
+        const int zs = z - (oz - 1);
+        if (wz && (zs < 0 || zs >= g.nz)) continue;
+        s += v[oz][0];
+        if (first) s += v[oz][1];
+        if (last) s += v[oz][2];
+    }
+    return s;
 }
 
 // Block (64, 4): each wavefront is 64 cells of one row, so y, z and every
@@ -972,18 +1039,33 @@ __global__ void __launch_bounds__(256) k_phi_merge(Geom g, Ptrs p, NextPhi q)
     for (int k = 0; k < MERGE_Z; ++k) {
         const int z = z0 + k;
         if (z >= g.nz) break;
-        T s = 0;
-#pragma unroll
-        for (int oz = 0; oz < 3; ++oz) {
-            // the same terms, in the same order, as when each is present
-            const int zs = z - (oz - 1);
-            if (wz && (zs < 0 || zs >= g.nz)) continue;
-            s += v[k][oz][0];
-            if (first) s += v[k][oz][1];
-            if (last) s += v[k][oz][2];
-        }
-        *lane_ptr(static_cast<T *>(p.phi), (long long)(z * g.ny + y) * g.nx, x) = s;
+        *lane_ptr(static_cast<T *>(p.phi), (long long)(z * g.ny + y) * g.nx, x) =
+            nphi_merge_sum(g, v[k], z, first, last);
     }
+}
+
+// phi of cell (x, y, z) from its pieces, loaded one by one (batched form).
+template <typename T>
+__device__ __forceinline__ void nphi_merge_cell(const Geom &g, const Ptrs &p, const NextPhi &q,
+                                                int x, int y, int z)
+{
+    const int by = q.by, ntiles = g.ny / by;
+    const int t = y / by, r = y - t * by;
+    const bool wy = g.bcy == BC_WALL, wz = g.bcz == BC_WALL;
+    const bool first = r == 0 && (!wy || t > 0), last = r == by - 1 && (!wy || t < ntiles - 1);
+    const T *part = static_cast<const T *>(q.part);
+    const T *edge = static_cast<const T *>(q.edge);
+    const long long row = (long long)(z * g.ny + y) * g.nx;
+    T v[3][3];
+#pragma unroll
+    for (int oz = -1; oz <= 1; ++oz) {
+        const int zs = z - oz;
+        const bool ok = !(wz && (zs < 0 || zs >= g.nz));
+        v[oz + 1][0] = ok ? *lane_ptr(part, (oz + 1) * g.np + row, x) : T(0);
+        v[oz + 1][1] = ok && first ? *lane_ptr(edge, nphi_edge_at(g, ntiles, 0, oz, t, z, 0), x) : T(0);
+        v[oz + 1][2] = ok && last ? *lane_ptr(edge, nphi_edge_at(g, ntiles, 1, oz, t, z, 0), x) : T(0);
+    }
+    *lane_ptr(static_cast<T *>(p.phi), row, x) = nphi_merge_sum(g, v, z, first, last);
 }
 
 // ------------------------------------------------------------- fused step
@@ -1364,7 +1446,8 @@ __attribute__((amdgpu_waves_per_eu(PHI ? 1 : collide_waves<D, P, COLL>()))) kb_s
 {
     using T = typename P::T;
     const long long t = *tbase + step_off;
-    const int nt = *ntiles;
+    // the phi stage covers every domain, the update those without nphi_by
+    const int nt = PHI ? ntiles[1] : ntiles[0];
     for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
         const BatchTile tl = tiles[ti];
         // the domain's record by value: read once, not re-read after every
@@ -1382,12 +1465,57 @@ __attribute__((amdgpu_waves_per_eu(PHI ? 1 : collide_waves<D, P, COLL>()))) kb_s
         const int z = tl.z0;
         if constexpr (ROW) y = __builtin_amdgcn_readfirstlane(y);
         if (x >= g.nx || y >= g.ny || z >= tl.z1) continue;
+        const int nby = doms[tl.dom].nphi_by;
         if constexpr (PHI) {
-            phi_cell<D, P, NbOf<ROW>>(g, p, x, y, z);
+            if (D == 3 && nby && t >= doms[tl.dom].nphi_from)
+                nphi_merge_cell<T>(g, p, NextPhi{doms[tl.dom].npart,
+                                                 doms[tl.dom].nedge, nby}, x, y, z);
+            else
+                phi_cell<D, P, NbOf<ROW>>(g, p, x, y, z);
         } else {
             const Phys<T> ph = to_phys<T>(doms[tl.dom].ph);
             collide_cell<D, P, COLL, NbOf<ROW>>(g, ph, p, x, y, z);
         }
+    }
+}
+
+// Batched phi-summing update for domains with rows of BX cells (64, 128,
+// 192 or 256): blocks stride over the ntiles[3 + 2k] tiles from index
+// ntiles[2 + 2k], k = BX / 64 - 1 (domain, rows y0 .. y0 + nphi_by - 1 of
+// plane z0), each an nphi_tile of its domain.  (A loop over several planes
+// per tile keeps the tile's pointers and parameters live across the update
+// and spills: measured slower even for one plane.)  FP32: at most 80 VGPRs (six
+// wavefronts per SIMD), so that three tiles fit a CU as in the
+// single-domain kernel.
+template <class P, int COLL>
+constexpr int kb_nphi_waves()
+{
+    return collide_waves<3, P, COLL>() == 4 ? 6 : collide_waves<3, P, COLL>();
+}
+
+template <class P, int COLL, int BX>
+__global__ void __launch_bounds__(NPHI_THREADS) __attribute__((amdgpu_waves_per_eu(kb_nphi_waves<P, COLL>())))
+kb_collide_nphi(const BatchDom *__restrict__ doms, const BatchTile *__restrict__ tiles,
+                const int *ntiles, const long long *tbase, int step_off)
+{
+    using T = typename P::T;
+    extern __shared__ double nphi_lds[];
+    constexpr int k = BX / 64 - 1;
+    const long long t = *tbase + step_off;
+    const int n0 = ntiles[2 + 2 * k], nt = ntiles[3 + 2 * k];
+    for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
+        const BatchTile tl = tiles[n0 + ti];
+        const Geom g = doms[tl.dom].g;  // by value, see kb_step
+        const long long first = doms[tl.dom].first, last = doms[tl.dom].last;
+        if (t < first || t >= last) continue;  // the whole block
+        const Ptrs p = batch_ptrs(doms[tl.dom], int((t - first) & 1), t >= doms[tl.dom].hist_from);
+        const Phys<T> ph = to_phys<T>(doms[tl.dom].ph);
+        const NextPhi q{doms[tl.dom].npart, doms[tl.dom].nedge, doms[tl.dom].nphi_by};
+        const int tid = int(threadIdx.x);
+        const int ty = __builtin_amdgcn_readfirstlane(tid / BX);
+        nphi_tile<P, COLL, BX>(g, ph, p, q, reinterpret_cast<T *>(nphi_lds), BX, tl.y0 / q.by, ty,
+                               tid - ty * BX, tl.z0, ty < q.by);
+        __syncthreads();  // the next tile of this block reuses the LDS
     }
 }
 
@@ -1652,33 +1780,65 @@ hipError_t launch_field(const Ctx &c, int field, double *dst)
     });
 }
 
+int nphi_block_threads(int storage) { return nphi_threads(storage); }
+
 hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool fused,
                              const BatchDom *doms, const BatchTile *tiles, const int *ntiles,
-                             const long long *tbase, int step_off, dim3 block, int grid,
+                             const long long *tbase, int step_off, dim3 block, const int *grid,
                              hipStream_t stream)
 {
     Ctx c{};
     c.dim = dim;
     c.storage = storage;
-    auto go = [&](auto k, dim3 blk) {
-        hipLaunchKernelGGL(k, dim3(grid), blk, 0, stream, doms, tiles, ntiles, tbase, step_off);
+
+    auto go = [&](auto k, dim3 blk, int nblk) {
+        hipLaunchKernelGGL(k, dim3(nblk), blk, 0, stream, doms, tiles, ntiles, tbase, step_off);
         return hipGetLastError();
+    };
+    // the phi-summing domains' update (plain phase-field storage only), one
+    // launch per row length present (grid[2 + k] blocks for NPHI_WIDTHS[k])
+    auto go_nphi = [&]<class P>(auto cc) -> hipError_t {
+        constexpr int COLL = decltype(cc)::value;
+        if constexpr (P::G::shifted) {
+            return hipErrorInvalidValue;
+        } else {
+            const int threads = nphi_threads(storage);
+            const size_t lds = size_t(26) * threads * sizeof(typename P::T);
+            auto one = [&](auto kernel, int nblk) {
+                if (nblk == 0) return hipSuccess;
+                hipLaunchKernelGGL(kernel, dim3(nblk), dim3(threads), lds, stream, doms, tiles,
+                                   ntiles, tbase, step_off);
+                return hipGetLastError();
+            };
+            hipError_t e = one(kb_collide_nphi<P, COLL, 64>, grid[2]);
+            if (e == hipSuccess) e = one(kb_collide_nphi<P, COLL, 128>, grid[3]);
+            if (e == hipSuccess) e = one(kb_collide_nphi<P, COLL, 192>, grid[4]);
+            if (e == hipSuccess) e = one(kb_collide_nphi<P, COLL, 256>, grid[5]);
+            return e;
+        }
     };
     // collision: the operator code (bit 0 flow collision, bit 1 first-order
     // phase-field equilibrium), shared by every domain of the batch
     return dispatch(c, [&]<int D, class P>() {
         if constexpr (D == 3) {
-            if (fused && collision == 0) return go(kb_fused<3, P, 0>, dim3(FUSED_THREADS));
-            if (fused && collision == 2) return go(kb_fused<3, P, 2>, dim3(FUSED_THREADS));
+            if (fused && collision == 0) return go(kb_fused<3, P, 0>, dim3(FUSED_THREADS), grid[0]);
+            if (fused && collision == 2) return go(kb_fused<3, P, 2>, dim3(FUSED_THREADS), grid[0]);
         }
         if (fused) return hipErrorInvalidValue;
-        hipError_t e = row ? go(kb_step<D, P, 0, true, true>, block)
-                           : go(kb_step<D, P, 0, true, false>, block);
+        hipError_t e = row ? go(kb_step<D, P, 0, true, true>, block, grid[0])
+                           : go(kb_step<D, P, 0, true, false>, block, grid[0]);
         if (e != hipSuccess) return e;
         return with_coll(collision, [&](auto cc) {
             constexpr int COLL = decltype(cc)::value;
-            return row ? go(kb_step<D, P, COLL, false, true>, block)
-                       : go(kb_step<D, P, COLL, false, false>, block);
+            hipError_t e2 = row ? go(kb_step<D, P, COLL, false, true>, block, grid[1])
+                                : go(kb_step<D, P, COLL, false, false>, block, grid[1]);
+            const bool nphi = grid[2] || grid[3] || grid[4] || grid[5];
+            if constexpr (D == 3) {
+                if (e2 == hipSuccess && nphi) e2 = go_nphi.template operator()<P>(cc);
+            } else {
+                if (nphi) e2 = hipErrorInvalidValue;
+            }
+            return e2;
         });
     });
 }

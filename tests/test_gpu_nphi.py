@@ -9,8 +9,9 @@ itself run to run and across block shapes (the summing kernel's tiles are
 whole rows by as many rows as 512 threads (256 with FP64) allow, dividing
 ny, whatever the block of the other kernels).  Cases cover tiles of one to
 eight rows, walls and periodic wrap in y and z, one-tile-high lattices (the
-edge sums wrap onto the same tile), and the transitions that must fall back
-to the pull sum (first step, a step without partial sums, a batch run)."""
+edge sums wrap onto the same tile), the transitions that must fall back to
+the pull sum (first step, a step without partial sums), and the batched
+form, which sums phi the same way and must give the same bits."""
 import numpy as np
 import pytest
 
@@ -141,8 +142,7 @@ def test_selection_and_fallbacks():
 
 
 def test_batch_run_then_solo_steps():
-    # partial sums written before a batch run are stale after it: the next
-    # solo step must sum the pulled populations again
+    # partial sums carried from solo steps into a batch run and back out
     params, phi, u, p = random_case(3, (64, 8, 6), (0, 0, 1), seed=47)
     po, f, g = noisy_state(params, phi, u, p, seed=53, amp=0.03)
     b = mplb.Batch(3, "fp64", capacity=2, max_tiles=1 << 14)
@@ -171,3 +171,75 @@ def test_first_order_equilibrium_with_partial_sums():
     f3, g3 = oracle.step(po, f, g, 3)
     assert rel_err(from_abi(3, s.get_populations(0)), f3) < 1e-12
     assert rel_err(from_abi(3, s.get_populations(1)), g3) < 1e-12
+
+
+def nphi_batch_cases(storage_seed=0):
+    # x-periodic domains whose update sums phi (rows of 64 / 128 / 192 cells)
+    # beside ones that do not (48-wide rows), walls and periodic wrap in y, z
+    spec = [((64, 8, 6), (0, 0, 1)), ((128, 4, 5), (0, 0, 0)), ((48, 8, 6), (0, 1, 1)),
+            ((64, 12, 4), (0, 1, 1)), ((192, 2, 3), (0, 0, 1))]
+    out = []
+    for k, (n, bc) in enumerate(spec):
+        params, phi, u, p = random_case(3, n, bc, seed=100 + k + storage_seed)
+        out.append((params, phi, u, p))
+    return out
+
+
+def batch_solver(case, storage, stream):
+    params, phi, u, p = case
+    s = mplb.Solver(params, storage=storage, stream=stream)
+    s.init(phi, u, p)
+    return s
+
+
+@pytest.mark.parametrize("storage,chunk", [("fp32", 0), ("fp32", 4), ("fp64", 4)])
+def test_batch_with_phi_summing_domains_equals_alone_bitwise(storage, chunk):
+    cases = nphi_batch_cases()
+    steps = 7
+    alone = []
+    for c in cases:
+        s = batch_solver(c, storage, None)
+        s.step(steps)
+        alone.append((s.get_populations(0), s.get_populations(1), s.fields()["phi"]))
+    b = mplb.Batch(3, storage, capacity=8, max_tiles=1 << 16)
+    b.set_graph_chunk(chunk)
+    solvers = [batch_solver(c, storage, b.stream) for c in cases]
+    assert [s.uses_phi_partials() for s in solvers] == [True, True, False, True, True]
+    for s in solvers:
+        b.attach(s, steps)
+    b.step(steps + 3)
+    for k, (s, want) in enumerate(zip(solvers, alone)):
+        got = (s.get_populations(0), s.get_populations(1), s.fields()["phi"])
+        for j in range(3):
+            assert np.array_equal(got[j], want[j]), (storage, k, j)
+
+
+def test_batch_windows_and_solo_steps_around_them_equal_alone():
+    # solo steps (leaving partial sums), a batch window opened mid-batch, solo
+    # steps after it: the same bits as one solo run of the same length
+    cases = nphi_batch_cases(storage_seed=7)
+    plan = [(2, 0, 3, 2), (0, 1, 4, 1), (1, 2, 2, 3), (3, 0, 5, 0), (0, 3, 3, 2)]
+    alone = []
+    for c, (pre, _, n, post) in zip(cases, plan):
+        s = batch_solver(c, "fp32", None)
+        s.step(pre + n + post)
+        alone.append((s.get_populations(0), s.get_populations(1)))
+    b = mplb.Batch(3, "fp32", capacity=8, max_tiles=1 << 16)
+    b.set_graph_chunk(2)
+    solvers = [batch_solver(c, "fp32", b.stream) for c in cases]
+    for s, (pre, _, _, _) in zip(solvers, plan):
+        s.step(pre)
+    slots = {}
+    for t in range(8):
+        for i, (_, at, n, _) in enumerate(plan):
+            if t == at:
+                slots[i] = b.attach(solvers[i], n)
+        b.step(1)
+    for i, sl in slots.items():
+        assert b.remaining(sl) == 0
+        b.detach(sl)
+    for i, (s, (pre, _, n, post)) in enumerate(zip(solvers, plan)):
+        s.step(post)
+        assert s.steps_done() == pre + n + post
+        fa, ga = s.get_populations(0), s.get_populations(1)
+        assert np.array_equal(fa, alone[i][0]) and np.array_equal(ga, alone[i][1]), i
