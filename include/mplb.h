@@ -189,8 +189,9 @@ int mplb_set_block(mplb_solver *s, int32_t bx, int32_t by, int32_t bz);
  * cells per row, a step can be a single kernel that computes phi into
  * on-chip memory and updates the cells from it, instead of a phi pass plus
  * the update (same arithmetic, same results).  mode 0: never; 1 (default):
- * where it is the faster form (the FP16 storage formats); 2: wherever it
- * applies.  Errors: EINVAL (mode not 0, 1 or 2). */
+ * where it is the faster form (measured slower than the two-launch step in
+ * every storage format, so at present never); 2: wherever it applies.
+ * Errors: EINVAL (mode not 0, 1 or 2). */
 int mplb_set_fused(mplb_solver *s, int32_t mode);
 
 /* 1 if the next step of this solver runs as one launch, 0 if not; <0 on

@@ -203,7 +203,7 @@ struct mplb_solver {
     bool ready;
     bool attached;
     bool hist;  // (phi u) of the previous step is stored (first-order phase-field equilibrium)
-    int fuse;  // one-launch step: 0 never, 1 where faster (FP16 formats), 2 where it applies
+    int fuse;  // one-launch step: 0 never, 1 where faster (at present nowhere), 2 where it applies
     int nphi;  // update kernel that sums the next phi: 0 never, 1 where it applies
     bool nphi_valid;  // the last update wrote partial sums of the current phi
     dim3 block;
@@ -626,7 +626,7 @@ struct mplb_batch {
     dim3 block;
     int chunk;
     bool row;     // row-form kernels (see row_form_ok)
-    int fuse;     // one-launch step: 0 never, 1 where faster (FP16 formats), 2 where allowed
+    int fuse;     // one-launch step: 0 never, 1 where faster (at present nowhere), 2 where allowed
     bool fused;   // one-launch step over fused tiles
     long long t;  // batch steps taken
     hipGraphExec_t exec;

@@ -84,7 +84,7 @@ hipError_t launch_phi_merge(const Ctx &c, const NextPhi &q);
 // array (launch_phi refreshes it for readers).
 bool fused_ok(const Ctx &c);
 bool fused_ok_geom(int dim, int collision, const Geom &g);
-// Storage formats for which the fused step is the faster one.
+// Storage formats for which the fused step is the faster one (none at present).
 bool fused_preferred(int storage);
 // Rows per tile of the fused kernel for rows of nx cells (512 threads).
 int fused_rows(int nx);

@@ -952,8 +952,7 @@ __device__ __forceinline__ void nphi_tile(const Geom &g, const Phys<typename P::
     using T = typename P::T;
     const int bx = BX ? BX : bx_rt, RS = 26 * bx;
     const int y = __builtin_amdgcn_readfirstlane(t * q.by + ty);
-    // FP16 flow storage: the combined form (the split one spills its bases)
-    using NB = typename std::conditional<P::F::shifted, NbRowC, NbRow>::type;
+    using NB = NbRow;
     NB nb;
     T rest = 0;
     if (active) {
@@ -1693,10 +1692,11 @@ bool fused_ok_geom(int dim, int collision, const Geom &g)
 bool fused_ok(const Ctx &c) { return fused_ok_geom(c.dim, c.ph.collision, c.g); }
 
 // The fused step re-reads each cell's g (and the halo rows') after the phi
-// sum; at FP32 and FP64 the per-XCD L2 does not hold a tile's planes that
-// long and the re-reads cost more than the phi pass they replace (measured
-// 974 vs 846 us at 128x128x512 FP32).  With FP16 populations it wins.
-bool fused_preferred(int storage) { return storage == ST_FP16S || storage == ST_FP16S_ALL; }
+// sum and marches its tiles plane by plane with two barriers per plane.  On
+// the 128x128x512 lattice it is slower than the two-launch forms in every
+// storage format (FP32 974 vs 725 us, FP64 1.84 vs 1.52 ms, FP16S 1.10 vs
+// 0.92 ms, FP16S_ALL 1.41 vs 1.19 ms), so it is never chosen by default.
+bool fused_preferred(int) { return false; }
 
 int fused_rows(int nx) { return FUSED_THREADS / fused_bx(nx); }
 

@@ -259,7 +259,8 @@ class Solver:
         check(self._lib.mplb_set_populations(self.h, int(which), _dptr(a)))
 
     def set_fused(self, mode=2):
-        """0: two-kernel step; 1: one-launch step where faster (FP16); 2: wherever it applies."""
+        """0: two-kernel step; 1: one-launch step where faster (at present nowhere); 2:
+        wherever it applies."""
         check(self._lib.mplb_set_fused(self.h, int(mode)))
 
     def uses_fused(self):
@@ -342,7 +343,8 @@ class Batch:
         check(self._lib.mplb_batch_set_graph_chunk(self.h, int(chunk)))
 
     def set_fused(self, mode=2):
-        """0: two-kernel step; 1: one-launch step where faster (FP16); 2: wherever it applies."""
+        """0: two-kernel step; 1: one-launch step where faster (at present nowhere); 2:
+        wherever it applies."""
         check(self._lib.mplb_batch_set_fused(self.h, int(mode)))
 
     def uses_fused(self):

@@ -338,10 +338,14 @@ def test_fused_step_equals_two_kernel_step_bitwise(storage, dim, n, bc):
 
 
 def test_fused_step_selection():
-    # default: the one-launch step for the FP16 formats only
+    # default: the two-launch step in every format (the one-launch step is
+    # the slower one); mode 2 takes it wherever it applies
     params, phi, u, p = random_case(3, (16, 4, 4), (0, 0, 1), seed=1)
-    assert not gpu_solver(params, "fp32", fields=(phi, u, p)).uses_fused()
-    assert gpu_solver(params, "fp16s", fields=(phi, u, p)).uses_fused()
+    for storage in ("fp32", "fp64", "fp16s", "fp16s_all"):
+        s = gpu_solver(params, storage, fields=(phi, u, p))
+        assert not s.uses_fused(), storage
+        s.set_fused(2)
+        assert s.uses_fused(), storage
     params, phi, u, p = random_case(3, (300, 4, 4), (0, 0, 1), seed=1)
     s = gpu_solver(params, "fp32", fields=(phi, u, p))
     s.set_fused(2)
