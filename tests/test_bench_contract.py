@@ -37,3 +37,15 @@ def test_algorithmic_bytes_follow_the_storage_sizes():
     assert bench.ALG_BYTES[("fp32", 3)]["fused"] == 27 * 4 * 4
     assert bench.ALG_BYTES[("fp64", 3)]["collide"] == 2 * bench.ALG_BYTES[("fp32", 3)]["collide"]
     assert bench.ALG_BYTES[("fp32", 2)]["method"] == 9 * 4 * 4 + 8
+
+
+def test_phi_summing_update_bytes():
+    # the update's 436 B plus its partial sums: three per cell and three more
+    # per cell of a tile's two edge rows; the merge reads them and writes phi
+    assert bench.nphi_bytes("fp32", 4) == (436 + 4 * 4.5, 4 * 4.5 + 4)
+    assert bench.nphi_bytes("fp32", 1) == (436 + 4 * 9, 4 * 9 + 4)
+    up, merge = bench.nphi_bytes("fp64", 2)
+    assert up == 872 + 8 * 6 and merge == 8 * 6 + 8
+    # a step moves more than the method's minimum, less than with the phi pass
+    ab = bench.ALG_BYTES[("fp32", 3)]
+    assert ab["method"] < sum(bench.nphi_bytes("fp32", 4)) < ab["collide"] + ab["phi"]
