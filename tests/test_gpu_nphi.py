@@ -37,6 +37,10 @@ CASES = [
     ((192, 2, 3), (0, 1, 1)),    # three wavefronts per row; 1 / 2
     ((128, 8, 5), (0, 1, 1)),    # 2 / 4 rows, two tiles between walls
     ((64, 16, 4), (0, 0, 1)),    # 4 / 8 rows, two tiles, periodic y
+    ((64, 1, 3), (0, 0, 1)),     # one row: both edge sums wrap onto it
+    ((64, 1, 3), (0, 1, 0)),     # one row between walls in y
+    ((128, 4, 1), (0, 0, 1)),    # one plane between walls in z (both z faces bounce)
+    ((64, 1, 1), (0, 0, 0)),     # one row, one plane, fully periodic
 ]
 
 
