@@ -10,8 +10,11 @@
 //              closure (density, chemical potential, forces, normal), flow
 //              collision, phase-field collision, post-collision values
 //              stored at the cell (pull streaming: the next step gathers);
-// or one launch, k_fused, that keeps phi in LDS (see "fused step" below).
-// The batched forms (kb_step, kb_fused) run the same per-cell bodies over a
+// or, where the lattice allows it, k_phi_merge (phi from partial sums) and
+// k_collide_nphi (the same update, which also sums the next phi from the
+// values it stores; see "next order parameter" below); or one launch,
+// k_fused, that keeps phi in LDS (see "fused step" below).  The batched forms
+// (kb_step, kb_collide_nphi, kb_fused) run the same per-cell bodies over a
 // tile list of many independent domains.
 //
 // Flow collision.  All cumulant rates other than the viscous ones are unity
@@ -1413,8 +1416,8 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double *part
 // a tile list (one block per tile when the launch has a block per tile); each
 // tile names its domain, whose geometry, parameters, buffers and active step
 // window are read from the domain table.  The per-cell arithmetic is the
-// single-domain path's (phi_cell, collide_cell, fused_tile), so a domain's
-// result does not depend on the batch it is in.
+// single-domain path's (phi_cell, collide_cell, nphi_merge_sum, nphi_tile,
+// fused_tile), so a domain's result does not depend on the batch it is in.
 
 __device__ __forceinline__ Ptrs batch_ptrs(const BatchDom &d, int in, bool have_prev)
 {
