@@ -200,10 +200,11 @@ int mplb_uses_fused(const mplb_solver *s);
 
 /* Next order parameter from partial sums (Sec. 2.2: phi at a cell is the
  * zeroth moment of the populations pulled there).  On 3-D lattices periodic
- * in x with nx a multiple of 64 up to 256, y and z periodic or walls, and
- * plain phase-field storage (FP64, FP32, FP16S), the update kernel works on
- * tiles of whole rows (as many rows as 512 threads, 256 with FP64, allow,
- * dividing ny), sums each cell's stored phase-field values towards the cells
+ * in x with nx a multiple of 64 up to 256 (or 512 with FP32 storage), y and
+ * z periodic or walls, and plain phase-field storage (FP64, FP32, FP16S),
+ * the update kernel works on tiles of whole rows (as many rows as 512
+ * threads, 256 with FP64 and FP16S, allow, dividing ny), sums each cell's
+ * stored phase-field values towards the cells
  * they stream to while it holds them, and the next step merges a few partial
  * sums per cell instead of re-reading all Q pulled values.  The sums run in
  * another order than the pull sum, so results agree with mode 0 to

@@ -89,7 +89,8 @@ bool nphi_geom(const mplb_params *p)
 {
     auto per_or_wall = [](int b) { return b == MPLB_BC_PERIODIC || b == MPLB_BC_WALL; };
     return p->dim == 3 && p->storage != MPLB_STORE_FP16S_ALL && p->bc[0] == MPLB_BC_PERIODIC &&
-           per_or_wall(p->bc[1]) && per_or_wall(p->bc[2]) && p->n[0] % 64 == 0 && p->n[0] <= 256;
+           per_or_wall(p->bc[1]) && per_or_wall(p->bc[2]) &&
+           mplb::nphi_width_ok(p->n[0], p->storage);
 }
 
 Layout make_layout(const mplb_params *p)
@@ -620,9 +621,10 @@ struct mplb_batch {
     // block tiles of the phi-summing domains (phi stage only); then
     // ntiles_nphi_host tiles of the phi-summing update
     int ntiles_host, ntiles_phi_host, ntiles_nphi_host;
-    int counts[10];  // the device tile counters (see launch_batch_step)
-    int grid[6];  // blocks of the phi, update and four phi-summing update launches: tile
-                  // counts rounded up to buckets of 4096 (0 for an empty group)
+    int counts[2 + 2 * mplb::NPHI_GROUPS];  // the device tile counters (see launch_batch_step)
+    int grid[2 + mplb::NPHI_GROUPS];  // blocks of the phi, update and phi-summing update
+                                      // launches: tile counts rounded up to buckets of 4096
+                                      // (0 for an empty group)
     dim3 block;
     int chunk;
     bool row;     // row-form kernels (see row_form_ok)
@@ -691,8 +693,8 @@ int upload_tables(mplb_batch *b)
         return true;
     };
     int seg[3] = {0, 0, 0};
-    int wstart[4] = {0, 0, 0, 0}, wcount[4] = {0, 0, 0, 0};  // phi-summing tiles by row length
-    for (int pass = 0; pass < 6; ++pass) {
+    int wstart[mplb::NPHI_GROUPS] = {}, wcount[mplb::NPHI_GROUPS] = {};  // phi-summing tiles by row length
+    for (int pass = 0; pass < 2 + mplb::NPHI_GROUPS; ++pass) {
         const size_t before = b->tiles.size();
         for (int i = 0; i < b->capacity; ++i) {
             const mplb_solver *s = b->slot[i];
@@ -710,8 +712,8 @@ int upload_tables(mplb_batch *b)
                 continue;
             }
             if (pass >= 2) {
-                // one group per row length 64, 128, 192, 256
-                if (!nby || nx != 64 * (pass - 1)) continue;
+                // one group per row length (nphi_group)
+                if (!nby || nx != mplb::nphi_group_width(pass - 2)) continue;
                 for (int z = 0; z < nz; ++z)
                     for (int y0 = 0; y0 < ny; y0 += nby)
                         if (!push(mplb::BatchTile{i, 0, y0, z, z + 1, nx}))
@@ -755,11 +757,12 @@ int upload_tables(mplb_batch *b)
         // attach / detach events (surplus blocks find no tile and exit)
         const int bucket = 4096;
         auto bucketed = [&](int n, int empty) { return n ? (n + bucket - 1) / bucket * bucket : empty; };
-        int grid[6] = {bucketed(b->ntiles_phi_host, bucket), bucketed(b->ntiles_host, bucket)};
-        for (int k = 0; k < 4; ++k) grid[2 + k] = bucketed(wcount[k], 0);
-        for (int k = 0; k < 6; ++k)
+        constexpr int NG = 2 + mplb::NPHI_GROUPS;
+        int grid[NG] = {bucketed(b->ntiles_phi_host, bucket), bucketed(b->ntiles_host, bucket)};
+        for (int k = 0; k < mplb::NPHI_GROUPS; ++k) grid[2 + k] = bucketed(wcount[k], 0);
+        for (int k = 0; k < NG; ++k)
             if (grid[k] != b->grid[k]) drop_graph(b);
-        for (int k = 0; k < 6; ++k) b->grid[k] = grid[k];
+        for (int k = 0; k < NG; ++k) b->grid[k] = grid[k];
     }
     if (row != b->row) drop_graph(b);  // a captured graph holds the other kernel
     b->row = row;
@@ -771,7 +774,7 @@ int upload_tables(mplb_batch *b)
                               hipMemcpyHostToDevice, b->stream));
     b->counts[0] = b->ntiles_host;
     b->counts[1] = b->ntiles_phi_host;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < mplb::NPHI_GROUPS; ++k) {
         b->counts[2 + 2 * k] = wstart[k];
         b->counts[3 + 2 * k] = wcount[k];
     }
@@ -827,7 +830,7 @@ int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t ma
     b->ntiles_host = b->ntiles_phi_host = b->ntiles_nphi_host = 0;
     // one bucket: an empty batch launches blocks that find no tile
     b->grid[0] = b->grid[1] = 4096;
-    for (int k = 2; k < 6; ++k) b->grid[k] = 0;
+    for (int k = 2; k < 2 + mplb::NPHI_GROUPS; ++k) b->grid[k] = 0;
     b->block = dim3(64, 4, 1);
     b->chunk = 16;
     b->t = 0;

@@ -69,12 +69,19 @@ struct NextPhi {
     int by;
 };
 // The update kernel that also sums the next order parameter from the values
-// it stores, tile by tile (3-D, x periodic with nx a multiple of 64 up to
-// 256, y and z periodic or walls, plain phase-field storage); nphi_ok tells
-// whether it applies.  Its tiles are whole rows by nphi_rows rows, whatever
+// it stores, tile by tile (3-D, x periodic, nx as nphi_width_ok, y and z
+// periodic or walls, plain phase-field storage); nphi_ok tells whether it
+// applies.  Its tiles are whole rows by nphi_rows rows, whatever
 // the block shape of the other kernels.
 bool nphi_ok(const Ctx &c);
 int nphi_rows(int nx, int ny, int storage);
+// Row lengths the phi-summing update takes: multiples of 64 up to 256, and
+// 512 with FP32 arithmetic (one row per 512-thread tile).
+bool nphi_width_ok(int nx, int storage);
+// Groups of the batched phi-summing update by row length 64, 128, 192, 256, 512.
+constexpr int NPHI_GROUPS = 5;
+constexpr int nphi_group_width(int k) { return k < 4 ? 64 * (k + 1) : 512; }
+constexpr int nphi_group(int nx) { return nx == 512 ? 4 : nx / 64 - 1; }
 hipError_t launch_collide_nphi(const Ctx &c, const NextPhi &q);
 // phi of the current level from the partial sums of the previous update.
 hipError_t launch_phi_merge(const Ctx &c, const NextPhi &q);
@@ -147,9 +154,9 @@ bool row_form_ok(int dim, const Geom &g, dim3 block);
 // then block tiles of the phi-summing domains up to ntiles[1] (their phi
 // stage merges partial sums), then the tiles of the phi-summing update
 // (domains with nphi_by > 0: whole rows of one plane), grouped by row length
-// 64, 128, 192, 256: group k starts at ntiles[2 + 2k] and holds ntiles[3 + 2k]
+// (nphi_group): group k starts at ntiles[2 + 2k] and holds ntiles[3 + 2k]
 // tiles.  grid[0], grid[1]: blocks of the phi stage and the update;
-// grid[2 + k]: of group k's update (0: not launched).
+// grid[2 + k]: of group k's update (0: not launched); 2 + NPHI_GROUPS entries.
 hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool fused,
                              const BatchDom *doms, const BatchTile *tiles, const int *ntiles,
                              const long long *tbase, int step_off, dim3 block, const int *grid,

@@ -865,6 +865,12 @@ k_collide(Geom g, Phys<typename P::T> ph, Ptrs p)
 // update holds too many registers for two 512-thread tiles per CU.
 constexpr int NPHI_THREADS = 512;
 static int nphi_threads(int storage) { return storage == ST_FP32 ? NPHI_THREADS : 256; }
+// Row lengths with a kernel (a multiple of 64 up to 256; 512, one row per
+// tile, where a tile has 512 threads).
+bool nphi_width_ok(int nx, int storage)
+{
+    return (nx % 64 == 0 && nx <= 256) || (nx == 512 && nphi_threads(storage) >= 512);
+}
 int nphi_rows(int nx, int ny, int storage)
 {
     const int cap = nphi_threads(storage) / nx;
@@ -1482,8 +1488,8 @@ __attribute__((amdgpu_waves_per_eu(PHI ? 1 : collide_waves<D, P, COLL>()))) kb_s
 }
 
 // Batched phi-summing update for domains with rows of BX cells (64, 128,
-// 192 or 256): blocks stride over the ntiles[3 + 2k] tiles from index
-// ntiles[2 + 2k], k = BX / 64 - 1 (domain, rows y0 .. y0 + nphi_by - 1 of
+// 192, 256 or 512): blocks stride over the ntiles[3 + 2k] tiles from index
+// ntiles[2 + 2k], k = nphi_group(BX) (domain, rows y0 .. y0 + nphi_by - 1 of
 // plane z0), each an nphi_tile of its domain.  (A loop over several planes
 // per tile keeps the tile's pointers and parameters live across the update
 // and spills: measured slower even for one plane.)  FP32: at most 80 VGPRs (six
@@ -1502,7 +1508,7 @@ kb_collide_nphi(const BatchDom *__restrict__ doms, const BatchTile *__restrict__
 {
     using T = typename P::T;
     extern __shared__ double nphi_lds[];
-    constexpr int k = BX / 64 - 1;
+    constexpr int k = nphi_group(BX);
     const long long t = *tbase + step_off;
     const int n0 = ntiles[2 + 2 * k], nt = ntiles[3 + 2 * k];
     for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
@@ -1636,7 +1642,7 @@ bool nphi_ok(const Ctx &c)
     const Geom &g = c.g;
     return c.dim == 3 && (c.storage == ST_FP64 || c.storage == ST_FP32 || c.storage == ST_FP16S) &&
            g.bcx == BC_PER && (g.bcy == BC_PER || g.bcy == BC_WALL) &&
-           (g.bcz == BC_PER || g.bcz == BC_WALL) && g.nx % 64 == 0 && g.nx <= 256 &&
+           (g.bcz == BC_PER || g.bcz == BC_WALL) && nphi_width_ok(g.nx, c.storage) &&
            27 * g.np < (1ll << 31);
 }
 
@@ -1668,6 +1674,10 @@ hipError_t launch_collide_nphi(const Ctx &c, const NextPhi &q)
                 case 128: return go(k_collide_nphi<P, COLL, 128>);
                 case 192: return go(k_collide_nphi<P, COLL, 192>);
                 case 256: return go(k_collide_nphi<P, COLL, 256>);
+                case 512:
+                    // one row per tile: 512 threads, FP32 only
+                    if constexpr (std::is_same<P, P32>::value) return go(k_collide_nphi<P, COLL, 512>);
+                    break;
                 }
                 return hipErrorInvalidValue;
             });
@@ -1817,6 +1827,11 @@ hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool
             if (e == hipSuccess) e = one(kb_collide_nphi<P, COLL, 128>, grid[3]);
             if (e == hipSuccess) e = one(kb_collide_nphi<P, COLL, 192>, grid[4]);
             if (e == hipSuccess) e = one(kb_collide_nphi<P, COLL, 256>, grid[5]);
+            if constexpr (std::is_same<P, P32>::value) {
+                if (e == hipSuccess) e = one(kb_collide_nphi<P, COLL, 512>, grid[6]);
+            } else {
+                if (grid[6]) e = hipErrorInvalidValue;
+            }
             return e;
         }
     };
@@ -1835,7 +1850,7 @@ hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool
             constexpr int COLL = decltype(cc)::value;
             hipError_t e2 = row ? go(kb_step<D, P, COLL, false, true>, block, grid[1])
                                 : go(kb_step<D, P, COLL, false, false>, block, grid[1]);
-            const bool nphi = grid[2] || grid[3] || grid[4] || grid[5];
+            const bool nphi = grid[2] || grid[3] || grid[4] || grid[5] || grid[6];
             if constexpr (D == 3) {
                 if (e2 == hipSuccess && nphi) e2 = go_nphi.template operator()<P>(cc);
             } else {

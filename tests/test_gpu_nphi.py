@@ -72,13 +72,16 @@ def test_partial_sums_match_oracle_fp64(n, bc):
 # FP16S: a round-off difference in phi can move a stored FP16 f' code by one
 # step (2^-11 of the encoded deviation), so its bar is that quantum
 @pytest.mark.parametrize("storage,tol", [("fp32", 2e-5), ("fp16s", 1e-3)])
-@pytest.mark.parametrize("n,bc", [CASES[0], CASES[2], CASES[3], CASES[7], CASES[8]])
+@pytest.mark.parametrize("n,bc", [CASES[0], CASES[2], CASES[3], CASES[7], CASES[8],
+                                  ((512, 3, 4), (0, 1, 1))])
 def test_partial_sums_match_pull_sum(storage, tol, n, bc):
     params, phi, u, p = random_case(3, n, bc, seed=sum(n) + 2)
     out = []
+    # rows of 512 cells: one row per 512-thread tile, FP32 only
+    summing = n[0] <= 256 or storage == "fp32"
     for mode in (1, 0):
         s = run(params, storage, None, (phi, u, p), 6, mode)
-        assert s.uses_phi_partials() == bool(mode)
+        assert s.uses_phi_partials() == (bool(mode) and summing)
         out.append((s.get_populations(0), s.get_populations(1), s.fields()["phi"]))
     for k in range(3):
         e = rel_err(out[0][k], out[1][k])
@@ -177,11 +180,14 @@ def test_first_order_equilibrium_with_partial_sums():
     assert rel_err(from_abi(3, s.get_populations(1)), g3) < 1e-12
 
 
-def nphi_batch_cases(storage_seed=0):
-    # x-periodic domains whose update sums phi (rows of 64 / 128 / 192 cells)
-    # beside ones that do not (48-wide rows), walls and periodic wrap in y, z
+def nphi_batch_cases(storage_seed=0, wide=False):
+    # x-periodic domains whose update sums phi (rows of 64 / 128 / 192 cells,
+    # and 512 with wide) beside ones that do not (48-wide rows), walls and
+    # periodic wrap in y, z
     spec = [((64, 8, 6), (0, 0, 1)), ((128, 4, 5), (0, 0, 0)), ((48, 8, 6), (0, 1, 1)),
             ((64, 12, 4), (0, 1, 1)), ((192, 2, 3), (0, 0, 1))]
+    if wide:
+        spec.append(((512, 2, 3), (0, 1, 1)))
     out = []
     for k, (n, bc) in enumerate(spec):
         params, phi, u, p = random_case(3, n, bc, seed=100 + k + storage_seed)
@@ -199,7 +205,8 @@ def batch_solver(case, storage, stream):
 @pytest.mark.parametrize("storage,chunk", [("fp32", 0), ("fp32", 4), ("fp64", 4), ("fp16s", 4),
                                            ("fp16s_all", 4)])
 def test_batch_with_phi_summing_domains_equals_alone_bitwise(storage, chunk):
-    cases = nphi_batch_cases()
+    wide = storage == "fp32"
+    cases = nphi_batch_cases(wide=wide)
     steps = 7
     alone = []
     for c in cases:
@@ -210,7 +217,8 @@ def test_batch_with_phi_summing_domains_equals_alone_bitwise(storage, chunk):
     b.set_graph_chunk(chunk)
     solvers = [batch_solver(c, storage, b.stream) for c in cases]
     summing = storage != "fp16s_all"  # FP16 phase-field storage: the phi pass
-    assert [s.uses_phi_partials() for s in solvers] == [summing, summing, False, summing, summing]
+    want = [summing, summing, False, summing, summing] + ([True] if wide else [])
+    assert [s.uses_phi_partials() for s in solvers] == want
     for s in solvers:
         b.attach(s, steps)
     b.step(steps + 3)
