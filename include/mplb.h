@@ -235,7 +235,7 @@ void mplb_destroy(mplb_solver *s);
  * Batches: many independent solvers of one dimension and storage format
  * advance together over a tile list that covers every attached lattice, one
  * block per tile: per step a phi launch and an update launch (one launch
- * with the fused step), plus one launch per row length (64, 128, 192, 256)
+ * with the fused step), plus one launch per row length (64, 128, 192, 256, 512)
  * for the solvers whose update sums the next phi (mplb_set_phi_partials).
  * Each attached solver has its own parameters, lattice size and activity
  * window; a solver's result is identical whether it is stepped alone or in
