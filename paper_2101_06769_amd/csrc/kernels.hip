@@ -932,18 +932,21 @@ __device__ __forceinline__ void nphi_gather(const Geom &g, const NextPhi &q,
                     s += V(b, ty, 1);
             }
         }
-        *lane_ptr(part, (long long)(oz + 1) * g.np + (zd * g.ny + y) * g.nx, x) = s;
+        // non-temporal, as the populations: the merge reads them a launch later
+        __builtin_nontemporal_store(s, lane_ptr(part, (long long)(oz + 1) * g.np + (zd * g.ny + y) * g.nx, x));
         if (ty == 0 && (!wy || t > 0)) {
             T e = 0;
 #pragma unroll
             for (int ox = -1; ox <= 1; ++ox) e += V((ox + 1) + 9 * (oz + 1), 0, ox + 1);
-            *lane_ptr(edge, nphi_edge_at(g, ntiles, 1, oz, t > 0 ? t - 1 : ntiles - 1, zd, 0), x) = e;
+            __builtin_nontemporal_store(
+                e, lane_ptr(edge, nphi_edge_at(g, ntiles, 1, oz, t > 0 ? t - 1 : ntiles - 1, zd, 0), x));
         }
         if (ty == by - 1 && (!wy || t < ntiles - 1)) {
             T e = 0;
 #pragma unroll
             for (int ox = -1; ox <= 1; ++ox) e += V((ox + 1) + 6 + 9 * (oz + 1), by - 1, ox + 1);
-            *lane_ptr(edge, nphi_edge_at(g, ntiles, 0, oz, t < ntiles - 1 ? t + 1 : 0, zd, 0), x) = e;
+            __builtin_nontemporal_store(
+                e, lane_ptr(edge, nphi_edge_at(g, ntiles, 0, oz, t < ntiles - 1 ? t + 1 : 0, zd, 0), x));
         }
     }
 }
