@@ -1050,8 +1050,9 @@ __global__ void __launch_bounds__(256) k_phi_merge(Geom g, Ptrs p, NextPhi q)
     for (int k = 0; k < MERGE_Z; ++k) {
         const int z = z0 + k;
         if (z >= g.nz) break;
-        *lane_ptr(static_cast<T *>(p.phi), (long long)(z * g.ny + y) * g.nx, x) =
-            nphi_merge_sum(g, v[k], z, first, last);
+        // non-temporal, as the partial sums: the next update reads phi a launch later
+        __builtin_nontemporal_store(nphi_merge_sum(g, v[k], z, first, last),
+                                    lane_ptr(static_cast<T *>(p.phi), (long long)(z * g.ny + y) * g.nx, x));
     }
 }
 
