@@ -574,7 +574,7 @@ __device__ __forceinline__ void phi_body(const NB &nb, long long np, const Ptrs 
     T s = 0;
 #pragma unroll
     for (int a = 0; a < Q; ++a) s += pull<D, typename P::G, T>(nb, p.Gin, np, a, p.gp_in, nullptr);
-    *lane_ptr(static_cast<T *>(p.phi), nb.row, nb.x) = s;
+    __builtin_nontemporal_store(s, lane_ptr(static_cast<T *>(p.phi), nb.row, nb.x));  // read a launch later
 }
 
 // x per lane; y and z wavefront-uniform when NB is NbRow.
@@ -1077,7 +1077,7 @@ __device__ __forceinline__ void nphi_merge_cell(const Geom &g, const Ptrs &p, co
         v[oz + 1][1] = ok && first ? *lane_ptr(edge, nphi_edge_at(g, ntiles, 0, oz, t, z, 0), x) : T(0);
         v[oz + 1][2] = ok && last ? *lane_ptr(edge, nphi_edge_at(g, ntiles, 1, oz, t, z, 0), x) : T(0);
     }
-    *lane_ptr(static_cast<T *>(p.phi), row, x) = nphi_merge_sum(g, v, z, first, last);
+    __builtin_nontemporal_store(nphi_merge_sum(g, v, z, first, last), lane_ptr(static_cast<T *>(p.phi), row, x));
 }
 
 // ------------------------------------------------------------- fused step
