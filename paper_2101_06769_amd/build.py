@@ -1,4 +1,6 @@
-"""Build libmplb.so (HIP, gfx950) in-tree with hipcc.
+"""Build libmplb.so (HIP, gfx950) in-tree with hipcc, and the standalone
+streaming-ceiling probe (stream_probe, an executable that prints the rates
+a kernel without arithmetic reaches on the update's access pattern).
 
     python -m paper_2101_06769_amd.build
 """
@@ -14,6 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmplb.so")
 SOURCES = ["kernels.hip", "api.cpp"]
+PROBE = os.path.join(HERE, "stream_probe")
 
 # hipcc flags: gfx950 only, C++20, no packed-FP32 instructions, and
 # multiply-add fusion only within one source expression (-ffp-contract=on):
@@ -33,16 +36,22 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include")] + \
-        [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+def _compile(args, target, verbose):
+    tmp = target + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + args + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, target)
+
+
+def build(verbose: bool = False) -> str:
+    _compile(HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include")] +
+             [os.path.join(CSRC, s) for s in SOURCES], LIB, verbose)
+    probe_flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")]
+    _compile(probe_flags + [os.path.join(CSRC, "stream_probe.hip")], PROBE, verbose)
     return LIB
 
 
