@@ -1,5 +1,5 @@
 #!/usr/bin/env python3
-"""Throughput of the fused multiphase lattice Boltzmann step on one MI355X.
+"""Throughput of the multiphase lattice Boltzmann step on one MI355X.
 
 Workload: 3-D Rayleigh-Taylor instability, D3Q27 cumulant flow + D3Q27
 conservative Allen-Cahn populations, 128 x 128 x 512 lattice, periodic in x/y,
@@ -8,11 +8,12 @@ z = 256 with a two-mode cosine perturbation of amplitude 0.05 * 128, FP32
 storage and arithmetic.  A "step" advances both population sets of every
 cell by one time step: the order parameter of the current level (merged from
 the partial sums the previous update wrote, or a pass over the pulled
-populations) plus the fused update of every cell.
+populations) plus the update of every cell (both collisions, streaming).
 
 Prints one JSON line: MLUPS (million lattice-cell updates per second) with a
-roofline entry for the dominant kernel (the fused update, HBM-bound) and the
-FP64 CPU oracle's rate on a bounded sample of the same workload.
+roofline entry for the dominant kernel (the cell update, HBM-bound), the
+error of the FP32 state against the FP64 CPU oracle on a slab of the same
+workload, and the oracle's own rate on that slab.
 """
 import argparse
 import json
@@ -29,21 +30,17 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # algorithmic bytes per cell for one launch of each kernel, FP32, D3Q27:
 #   collide: read 27 f' + 27 g + phi, write 27 f' + 27 g  -> 4 * (27 * 4 + 1) = 436
 #   phi:     read 27 g, write phi                          -> 4 * (27 + 1)     = 112
-ALG_BYTES = {("fp32", 3): {"collide": 436, "phi": 112, "method": 440, "fused": 432},
-             ("fp64", 3): {"collide": 872, "phi": 224, "method": 880, "fused": 864},
+ALG_BYTES = {("fp32", 3): {"collide": 436, "phi": 112, "method": 440},
+             ("fp64", 3): {"collide": 872, "phi": 224, "method": 880},
              # FP16-shifted flow set: 27 x 2 B each way, plus the per-cell shift
              # and scale (2 x 4 B) read at the source cells and written back
              ("fp16s", 3): {"collide": 2 * 27 * 2 + 2 * 27 * 4 + 4 + 2 * 8, "phi": 27 * 4 + 4,
-                            "method": 2 * 27 * 2 + 2 * 27 * 4 + 8 + 2 * 8,
-                            "fused": 2 * 27 * 2 + 2 * 27 * 4 + 2 * 8},
+                            "method": 2 * 27 * 2 + 2 * 27 * 4 + 8 + 2 * 8},
              # both sets FP16-shifted; the phase-field shift (phi, 4 B) too
              ("fp16s_all", 3): {"collide": 4 * 27 * 2 + 4 + 2 * 8 + 2 * 4, "phi": 27 * 2 + 4 + 4,
-                                "method": 4 * 27 * 2 + 8 + 2 * 8 + 2 * 4,
-                                "fused": 4 * 27 * 2 + 2 * 8 + 2 * 4},
+                                "method": 4 * 27 * 2 + 8 + 2 * 8 + 2 * 4},
              ("fp32", 2): {"collide": 4 * (2 * 2 * 9 + 1), "phi": 4 * (9 + 1), "method": 152},
              ("fp64", 2): {"collide": 8 * (2 * 2 * 9 + 1), "phi": 8 * (9 + 1), "method": 304}}
-# The one-launch step keeps phi on chip: its bytes are the populations' alone
-# (read and written once), which is also what the method must move per step.
 
 
 def nphi_bytes(storage, rows):
@@ -59,7 +56,6 @@ def nphi_bytes(storage, rows):
 
 KERNEL_SOURCES = ("kernels.hip", "lattice.hpp", "internal.h")
 TRAFFIC_PROFILES = {
-    "k_fused": os.path.join(ROOT, "profiles", "k_fused_rti3d_128x128x512_fp32_hbm_bytes.md"),
     "k_collide": os.path.join(ROOT, "profiles", "k_collide_k_phi_rti3d_128x128x512_fp32_hbm_bytes.md"),
     "k_collide_nphi": os.path.join(ROOT, "profiles",
                                    "k_collide_nphi_k_phi_merge_rti3d_128x128x512_fp32_hbm_bytes.md"),
@@ -88,12 +84,35 @@ def profiled_traffic(storage, nz, kernel="k_collide"):
     return rec["traffic_bytes_per_launch"]
 
 
+def cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(case_fn, min_seconds=10.0):
     """The FP64 oracle on a 128 x 128 x 128 slab of the same workload (the
-    interface region), stepped until at least min_seconds have elapsed."""
+    interface region), stepped on every host thread until at least
+    min_seconds have elapsed, then on one thread for one step of a
+    128 x 128 x 16 slab.  Returns the baseline record and the oracle's final
+    state (params, f, g, steps) for the error figure."""
     import oracle
 
-    case = case_fn(nz=128)
+    case = case_fn(128)
     p = oracle.params_from_dict(case.params)
     f, g = oracle.init(p, case.phi, case.u, case.p)
     steps, t0 = 0, time.perf_counter()
@@ -103,10 +122,55 @@ def cpu_baseline(case_fn, min_seconds=10.0):
         el = time.perf_counter() - t0
         if el >= min_seconds:
             break
-    return {"value": case.ncells * steps / el / 1e6, "unit": "MLUPS",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d step(s) of a 128x128x128 slab (%d cells) of the same Rayleigh-Taylor "
-                      "case, FP64, %.1f s" % (steps, case.ncells, el)}
+    threads = oracle.num_threads()
+    small = case_fn(16)
+    ps = oracle.params_from_dict(small.params)
+    fs, gs = oracle.init(ps, small.phi, small.u, small.p)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.step(ps, fs, gs, 1)
+        el1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    rec = {"value": case.ncells * steps / el / 1e6, "unit": "MLUPS",
+           "cores": threads, "kind": "oracle",
+           "sample": "%d step(s) of a 128x128x128 slab (%d cells) of the same Rayleigh-Taylor "
+                     "case, FP64, %.1f s on %d threads" % (steps, case.ncells, el, threads),
+           "cpu_model": cpu_model(),
+           "value_1thread": small.ncells / el1 / 1e6,
+           "sample_1thread": "1 step of a 128x128x16 slab (%d cells), FP64, %.1f s on 1 thread" %
+                             (small.ncells, el1)}
+    return rec, (p, f, g, steps)
+
+
+def error_vs_oracle(case, storage, ref):
+    """Per-field error of the GPU state against the FP64 oracle after the same
+    steps from the same initial state: max |dphi|, max |du| / U*, max |dp| /
+    (rho_h U*^2) with U* = sqrt(g L_x) = 0.06, the Rayleigh-Taylor velocity
+    scale.  The tolerances are the ones the tests state for this format."""
+    import oracle
+    from paper_2101_06769_amd import inputs, mplb
+
+    p, f, g, steps = ref
+    want = oracle.fields(p, f, g)
+    s = mplb.Solver(case.params, storage=storage)
+    s.init(case.phi, case.u, case.p)
+    s.step(steps)
+    got = s.fields()
+    U = inputs.U_STAR
+    err = {"phi": float(np.abs(got["phi"] - want["phi"]).max()),
+           "u_over_U": float(np.abs(got["u"] - want["u"]).max() / U),
+           "p_over_rhoU2": float(np.abs(got["p"] - want["p"]).max() / (U * U))}
+    return {"steps": steps, "cells": case.ncells, "max_abs": err,
+            "tolerance": ERROR_TOLERANCE.get(storage),
+            "within_tolerance": (all(err[k] <= ERROR_TOLERANCE[storage][k] for k in err)
+                                 if storage in ERROR_TOLERANCE else None)}
+
+
+# Per-field bars of the FP32 state against the FP64 oracle over the first few
+# steps (the same bars the parity tests hold): a few FP32 ulps per step.
+ERROR_TOLERANCE = {"fp32": {"phi": 1e-5, "u_over_U": 1e-5, "p_over_rhoU2": 1e-4}}
 
 
 def bench_batch(args):
@@ -223,10 +287,8 @@ def bench_splash(args):
         red, rc = s.reduce()
         rec = {"mlups": round(N * args.splash_steps / (ms / 1e3) / 1e6, 1),
                "ms_per_step": round(ms / args.splash_steps, 4),
-               "alg_GBs": round(ALG_BYTES[(storage.split("_floor")[0], 3)][
-                                    "fused" if s.uses_fused() else "method"] * N *
-                                args.splash_steps /
-                                (ms / 1e3) / 1e9, 1),
+               "alg_GBs": round(ALG_BYTES[(storage.split("_floor")[0], 3)]["method"] * N *
+                                args.splash_steps / (ms / 1e3) / 1e9, 1),
                "status": "ok" if rc == mplb.OK else "unstable",
                "phase_mass_rel_drift": abs(red[0] - case.phi.sum()) / case.phi.sum()}
         if ref is None:
@@ -451,9 +513,6 @@ def main():
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16s", "fp16s_all"])
     ap.add_argument("--nz", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fuse", type=int, default=1, choices=[0, 1, 2],
-                    help="one-launch step: 0 never (phi pass + update), 1 where it is the "
-                         "faster form (default), 2 wherever it applies")
     ap.add_argument("--phi-partials", type=int, default=1, choices=[0, 1],
                     help="1: the update sums the next phi from the values it stores and the "
                          "next step merges the partial sums (default, where it applies); 0: a "
@@ -519,7 +578,6 @@ def main():
     case = inputs.rti3d(nz=args.nz)
     N = case.ncells
     s = mplb.Solver(case.params, storage=args.storage)
-    s.set_fused(args.fuse)
     s.set_phi_partials(args.phi_partials)
     s.init(case.phi, case.u, case.p)
     s.step(args.warmup)
@@ -538,18 +596,18 @@ def main():
     red, rc = s.reduce()
     m0 = float(case.phi.sum())
     ab = ALG_BYTES[(args.storage, 3)]
-    fused = s.uses_fused()
     rows = s.phi_partial_rows()
-    if fused:
-        kernel, kbytes, phi_kernel = "k_fused", ab["fused"], None
-    elif rows:
+    if rows:
         kernel, phi_kernel = "k_collide_nphi", "k_phi_merge"
         kbytes = nphi_bytes(args.storage, rows)[0]
     else:
         kernel, kbytes, phi_kernel = "k_collide", ab["collide"], "k_phi"
-    method_bytes = ab["fused"] if fused else ab["method"]
+    method_bytes = ab["method"]
     t_col = ms_col / args.steps / 1e3
-    achieved = kbytes * N / t_col / 1e9
+    # roofline of the dominant kernel on the method's algorithmic bytes per
+    # cell (read and write every population once, write and read phi once);
+    # the kernel's own figure (its partial sums of phi included) beside it
+    achieved = method_bytes * N / t_col / 1e9
     line = {
         "metric": "MLUPS (flow+phase field) and % HBM roofline at fixed error vs FP64",
         "value": round(mlups, 1),
@@ -571,19 +629,24 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": profiled_traffic(args.storage, args.nz, kernel),
-                     "kernel": kernel, "alg_bytes_per_cell": kbytes,
+                     "kernel": kernel, "alg_bytes_per_cell": method_bytes,
+                     "kernel_bytes_per_cell": kbytes,
+                     "kernel_frac": round(kbytes * N / t_col / 1e9 / HBM_PEAK_GBS, 4),
                      "avg_launch_us": round(t_col * 1e6, 2),
                      "phi_stage_kernel": phi_kernel,
-                     "phi_stage_avg_launch_us": None if fused else round(ms_phi / args.steps * 1e3, 2)},
+                     "phi_stage_avg_launch_us": round(ms_phi / args.steps * 1e3, 2)},
         "method_alg_GBs": round(method_bytes * N * args.steps / (ms / 1e3) / 1e9, 1),
         "method_frac": round(method_bytes * N * args.steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "phase_mass_rel_drift": abs(red[0] - m0) / m0,
         "status": "ok" if rc == mplb.OK else "unstable",
     }
+    del s
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(lambda nz: inputs.rti3d(nz=nz, amp=0.05 * 128),
-                                            args.cpu_seconds)
-        line["cpu_baseline"]["gpu_speedup"] = round(mlups / line["cpu_baseline"]["value"], 1)
+        slab = lambda nz: inputs.rti3d(nz=nz, amp=0.05 * 128)  # noqa: E731
+        cpu, ref = cpu_baseline(slab, args.cpu_seconds)
+        cpu["gpu_speedup"] = round(mlups / cpu["value"], 1)
+        line["cpu_baseline"] = cpu
+        line["error_vs_fp64"] = error_vs_oracle(slab(128), args.storage, ref)
     print(json.dumps(line), flush=True)
 
 

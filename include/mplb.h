@@ -121,99 +121,134 @@ typedef struct mplb_params {
 
 typedef struct mplb_solver mplb_solver;
 
-/* Library version (MPLB_VERSION) and the device architecture it was built for. */
+/* Library version (MPLB_VERSION) and the device architecture it was built
+ * for.  Design, not in the paper. */
 int32_t mplb_version(void);
 const char *mplb_arch(void);
 
 /* Bytes of device memory a solver with these parameters needs (0 if the
- * parameters are invalid). */
+ * parameters are invalid; mplb_last_error says why).  The parameters are the
+ * paper's statement of the problem (Sec. 2.1: densities, viscosities,
+ * interface thickness W, mobility M, surface tension sigma; Sec. 3: lattice,
+ * gravity, boundary types); the memory layout is this library's design. */
 size_t mplb_state_bytes(const mplb_params *p);
 
 /* Validate p and bind a solver to the caller's arena and stream.
- * dev_arena: device pointer, 256-byte aligned, at least mplb_state_bytes(p).
+ * dev_arena: device pointer, 256-byte aligned, at least mplb_state_bytes(p)
+ * bytes, owned by the caller for the solver's lifetime.
  * hip_stream: a hipStream_t (NULL for the null stream).
- * Errors: EINVAL (bad parameters, see mplb_last_error), ENOMEM (arena too small). */
+ * Errors: EINVAL (bad parameters, see mplb_last_error), ENOMEM (arena too
+ * small).  Design, not in the paper. */
 int mplb_create(const mplb_params *p, void *dev_arena, size_t arena_bytes, void *hip_stream,
                 mplb_solver **out);
 
 /* Initial state from macroscopic fields (host, double): phi [N], u [dim][N],
- * p [N] (NULL = zero pressure).  Populations become the equilibria (Sec. 2.2,
- * 2.3, Appendix A) at the velocity u - F/(2 rho) and pressure p - sum(Xi)/2,
- * so that mplb_read returns exactly phi, u and p before the first step.
- * Resets the step counter.  Synchronises the stream. */
+ * p [N] (NULL = zero pressure).  Populations become the equilibria of
+ * Sec. 2.2 (phase field, Eq. LBM_AC with the Hermite terms of Appendix A)
+ * and Sec. 2.3 (flow, Eq. LMNA_distribution), taken at the velocity
+ * u - F/(2 rho) and pressure p - sum(Xi)/2, so that mplb_read returns exactly
+ * phi, u and p before the first step.  Resets the step counter and the
+ * history.  Synchronises the stream.  Errors: EINVAL, ESTATE (attached to a
+ * batch), EDEVICE. */
 int mplb_init(mplb_solver *s, const double *phi, const double *u, const double *p);
 
-/* Advance nsteps >= 0 time steps (asynchronous). */
+/* Advance nsteps >= 0 time steps (asynchronous).  One step is the paper's
+ * scheme from time n to n + 1: the order parameter as the zeroth moment of
+ * the phase-field populations (Sec. 2.2), its isotropic gradient and
+ * Laplacian (Sec. 2.2), density, chemical potential and forces (Sec. 2.1),
+ * the flow collision with its source term (Sec. 2.3, Eqs. LMNA_LBM to
+ * LMNA_distribution, cumulant relaxation), the phase-field collision with
+ * the antidiffusion source (Sec. 2.2, Eqs. LBM_AC and
+ * phase_source_post_discretization), and streaming with the boundary rules
+ * of Sec. 3 (half-way bounce-back walls, symmetry planes, periodic axes).
+ * Errors: EINVAL, ESTATE (not initialised, or attached to a batch),
+ * EDEVICE. */
 int mplb_step(mplb_solver *s, int64_t nsteps);
 
 /* As mplb_step, but records HIP events around every kernel launch on the
- * solver's stream and returns the summed device time of the two kernels of
- * the step (ms_phi: order-parameter pass; ms_collide: fused collision) in
+ * solver's stream and returns the summed device time of the two launches of
+ * each step (ms_phi: order-parameter stage; ms_collide: cell update) in
  * milliseconds.  Synchronises the stream.  For profiling; the events add a
- * few microseconds per step. */
+ * few microseconds per step.  Design, not in the paper.  Errors: as
+ * mplb_step. */
 int mplb_step_timed(mplb_solver *s, int64_t nsteps, double *ms_phi, double *ms_collide);
 
 /* Block until all queued work on the solver's stream has finished. */
 int mplb_sync(mplb_solver *s);
 
-/* Steps taken since mplb_init / mplb_set_populations. */
+/* Steps taken since mplb_init / mplb_set_populations (kept by mplb_load). */
 int64_t mplb_steps_done(const mplb_solver *s);
 
-/* One macroscopic field (MPLB_FIELD_*) of the state at time n into host_out[N].
- * Synchronises the stream. */
+/* One macroscopic field (MPLB_FIELD_*) of the state at time n into host_out[N]:
+ * phi = sum g (Sec. 2.2), rho(phi) linear (Sec. 2.3), u the first moment of
+ * f'/(rho cs^2) plus F/(2 rho) (Sec. 2.3), p = sum f' + sum(Xi)/2, the zeroth
+ * moment of Eq. LMNA_distribution with half the source (the reading this
+ * library takes of the pressure field).  Synchronises the stream.  Errors:
+ * EINVAL, ESTATE, EDEVICE. */
 int mplb_read(mplb_solver *s, int32_t field, double *host_out);
 
 /* FP64 reductions over the lattice, deterministic (fixed summation order):
- * out[0] = sum phi, out[1..3] = sum rho u, out[4] = max |u|.
- * Returns MPLB_EUNSTABLE if any phi, rho u or |u| is not finite.
- * Synchronises the stream. */
+ * out[0] = sum phi (the phase mass Sec. 2.2's conservative form keeps),
+ * out[1..3] = sum rho u, out[4] = max |u|.  Returns MPLB_EUNSTABLE if any
+ * phi, rho u or |u| is not finite.  Synchronises the stream.  The FP64
+ * reductions are this library's design, not in the paper. */
 int mplb_reduce(mplb_solver *s, double out[5]);
 
 /* Pre-collision populations of the state at time n (which: 0 = f', 1 = g),
- * host_out[Q][N] in the population order above.  Synchronises the stream. */
+ * host_out[Q][N] in the population order above, decoded to double.
+ * Synchronises the stream. */
 int mplb_get_populations(mplb_solver *s, int32_t which, double *host_out);
 
 /* Replace one population set of the state at time n (which: 0 = f', 1 = g)
- * with host_in[Q][N] (pre-collision values, population order above).
- * Synchronises the stream. */
+ * with host_in[Q][N] (pre-collision values, population order above),
+ * rounded to the storage format.  Synchronises the stream.  This is a state
+ * edit, not a resume: it resets the step counter, drops the (phi u) history
+ * of the first-order phase-field equilibrium and the partial sums of phi,
+ * and FP16 formats re-encode against the current references.  Use
+ * mplb_save / mplb_load to checkpoint and resume.  Errors: EINVAL, ESTATE
+ * (FP16 formats before mplb_init; attached to a batch), EDEVICE. */
 int mplb_set_populations(mplb_solver *s, int32_t which, const double *host_in);
 
-/* Threads per block of the two-kernel step (x, y, z); (0, 0, 0) = library
+/* Checkpoint and resume.  mplb_save_bytes: size of the host blob mplb_save
+ * writes for the solver's current state (0 for a NULL solver).  mplb_save
+ * copies into host_blob (at least that many bytes, caller-owned) everything
+ * a following step reads, in the stored representation: the population
+ * buffers of the current level, the per-cell references of the FP16
+ * formats, the (phi u) history, the partial sums of phi if the last update
+ * wrote them, the step counter and the launch settings, with a hash of the
+ * parameters.  mplb_load restores such a blob into a solver created with
+ * equal parameters (any arena); the loaded solver's later steps are bit for
+ * bit those the saved one would have taken.  Both synchronise the stream.
+ * Errors: EINVAL (NULL arguments, blob too small, another format or other
+ * parameters), ESTATE (save before mplb_init; load into an attached
+ * solver), EDEVICE.  Design, not in the paper. */
+size_t mplb_save_bytes(const mplb_solver *s);
+int mplb_save(mplb_solver *s, void *host_blob, size_t bytes);
+int mplb_load(mplb_solver *s, const void *host_blob, size_t bytes);
+
+/* Threads per block of the cell update (x, y, z); (0, 0, 0) = library
  * default (as wide in x as the lattice, up to 256).  Between 1 and 256
  * threads; bz = 1 in 2-D.  Blocks a multiple of 64 wide in x on lattices
  * periodic in x take wavefront-uniform (row-form) addressing; results do not
- * depend on the shape.  Errors: EINVAL. */
+ * depend on the shape.  Errors: EINVAL.  Design, not in the paper. */
 int mplb_set_block(mplb_solver *s, int32_t bx, int32_t by, int32_t bz);
 
-/* One-launch step: for 3-D cumulant lattices periodic in x with at most 256
- * cells per row, a step can be a single kernel that computes phi into
- * on-chip memory and updates the cells from it, instead of a phi pass plus
- * the update (same arithmetic, same results).  mode 0: never; 1 (default):
- * where it is the faster form (measured slower than the two-launch step in
- * every storage format, so at present never); 2: wherever it applies.
- * Errors: EINVAL (mode not 0, 1 or 2). */
-int mplb_set_fused(mplb_solver *s, int32_t mode);
-
-/* 1 if the next step of this solver runs as one launch, 0 if not; <0 on
- * error. */
-int mplb_uses_fused(const mplb_solver *s);
-
-/* Next order parameter from partial sums (Sec. 2.2: phi at a cell is the
- * zeroth moment of the populations pulled there).  On 3-D lattices periodic
- * in x with nx a multiple of 64 up to 256 (or 512 with FP32 storage), y and
- * z periodic or walls, and plain phase-field storage (FP64, FP32, FP16S),
- * the update kernel works on tiles of whole rows (as many rows as 512
- * threads, 256 with FP64 and FP16S, allow, dividing ny), sums each cell's
- * stored phase-field values towards the cells
- * they stream to while it holds them, and the next step merges a few partial
- * sums per cell instead of re-reading all Q pulled values.  The sums run in
- * another order than the pull sum, so results agree with mode 0 to
- * round-off, not bit for bit (they do not depend on the block shape set by
+/* Next order parameter from partial sums.  phi at a cell is the zeroth
+ * moment of the phase-field populations pulled there (Sec. 2.2); on 3-D
+ * lattices periodic in x with nx a multiple of 64 up to 256 (or 512 with
+ * FP32 storage), y and z periodic or walls, and plain phase-field storage
+ * (FP64, FP32, FP16S), the update kernel works on tiles of whole rows (as
+ * many rows as 512 threads, 256 with FP64 and FP16S, allow, dividing ny),
+ * sums each cell's stored phase-field values towards the cells they stream
+ * to while it holds them, and the next step merges a few partial sums per
+ * cell instead of re-reading all Q pulled values.  The sums run in another
+ * order than the pull sum, so results agree with mode 0 to round-off, not
+ * bit for bit (they do not depend on the block shape set by
  * mplb_set_block).  The first step after mplb_init, mplb_set_populations or
  * a step in mode 0 uses the pull sum.  A batch (mplb_batch_*) steps such a
  * solver the same way, with the same bits; partial sums carry into and out
- * of a batch run.  mode 0: never; 1 (default): wherever it applies (not
- * with the one-launch step).  Errors: EINVAL. */
+ * of a batch run.  mode 0: never; 1 (default): wherever it applies.
+ * Errors: EINVAL, ESTATE (attached to a batch).  Design, not in the paper. */
 int mplb_set_phi_partials(mplb_solver *s, int32_t mode);
 
 /* Rows per tile (>= 1) if the next update of this solver writes partial
@@ -224,7 +259,9 @@ int mplb_uses_phi_partials(const mplb_solver *s);
  * `steps` steps after two warm-up steps, device time from HIP events), select
  * the fastest, and write it to best[3].  The solver is advanced by the timed
  * steps, so tune on a scratch solver of representative size.  candidates is
- * an array of ncand (bx, by, bz) triples, or NULL for the built-in list. */
+ * an array of ncand (bx, by, bz) triples, or NULL for the built-in list.
+ * Errors: EINVAL, ESTATE (attached to a batch), EDEVICE.  Design, not in
+ * the paper. */
 int mplb_tune_block(mplb_solver *s, int32_t steps, const int32_t *candidates, int32_t ncand,
                     int32_t best[3], double *best_ms_per_step);
 
@@ -232,17 +269,17 @@ int mplb_tune_block(mplb_solver *s, int32_t steps, const int32_t *candidates, in
 void mplb_destroy(mplb_solver *s);
 
 /* ---------------------------------------------------------------------------
- * Batches: many independent solvers of one dimension and storage format
- * advance together over a tile list that covers every attached lattice, one
- * block per tile: per step a phi launch and an update launch (one launch
- * with the fused step), plus one launch per row length (64, 128, 192, 256, 512)
- * for the solvers whose update sums the next phi (mplb_set_phi_partials).
- * Each attached solver has its own parameters, lattice size and activity
- * window; a solver's result is identical whether it is stepped alone or in
- * a batch (same per-cell arithmetic, same step form).  Steps are replayed
- * from a captured hipGraph in chunks of `graph_chunk` steps.  max_tiles
- * bounds the tile list: per solver about N / (block threads) block tiles,
- * plus ny nz / rows tiles where the update sums phi.
+ * Batches (design, not in the paper): many independent solvers of one
+ * dimension and storage format advance together over a tile list that covers
+ * every attached lattice, one block per tile: per step a phi launch and an
+ * update launch, plus one launch per row length (64, 128, 192, 256, 512) for
+ * the solvers whose update sums the next phi (mplb_set_phi_partials).  Each
+ * attached solver has its own parameters, lattice size and activity window;
+ * a solver's result is identical whether it is stepped alone or in a batch
+ * (same per-cell arithmetic, same step form).  Steps are replayed from a
+ * captured hipGraph in chunks of `graph_chunk` steps.  max_tiles bounds the
+ * tile list: per solver about N / (block threads) block tiles, plus
+ * ny nz / rows tiles where the update sums phi.
  * ------------------------------------------------------------------------- */
 typedef struct mplb_batch mplb_batch;
 
@@ -250,29 +287,19 @@ typedef struct mplb_batch mplb_batch;
  * tiles in total. */
 size_t mplb_batch_table_bytes(int32_t capacity, int64_t max_tiles);
 
-/* dev_table: 256-byte aligned device memory of mplb_batch_table_bytes();
- * hip_stream: a created (non-NULL) stream, which must also be the stream of
- * every solver that will be attached (step chunks are captured from it). */
+/* dev_table: 256-byte aligned device memory of mplb_batch_table_bytes(),
+ * caller-owned; hip_stream: a created (non-NULL) stream, which must also be
+ * the stream of every solver that will be attached (step chunks are captured
+ * from it).  Errors: EINVAL, ENOMEM (table too small), EDEVICE. */
 int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t max_tiles,
                       void *dev_table, size_t table_bytes, void *hip_stream, mplb_batch **out);
 
 /* Block (= tile) shape of the batched kernels; at most 256 threads.
- * Rebuilds the tile list. */
+ * Rebuilds the tile list.  Errors: EINVAL, ENOMEM (tile list full). */
 int mplb_batch_set_block(mplb_batch *b, int32_t bx, int32_t by, int32_t bz);
 
 /* Graph chunk in steps (>= 1), or 0 to launch every step directly. */
 int mplb_batch_set_graph_chunk(mplb_batch *b, int32_t chunk);
-
-/* One-launch batched step, modes as mplb_set_fused (default 1): when chosen
- * and every attached domain allows it, each batch step is one kernel over
- * tiles of whole rows; otherwise the phi pass and the update over block
- * tiles.  Same arithmetic, same results.  Rebuilds the tile list.  Errors:
- * EINVAL, ENOMEM (tile list full). */
-int mplb_batch_set_fused(mplb_batch *b, int32_t mode);
-
-/* 1 if the batch currently steps with the one-launch kernel, 0 if not, <0
- * on error. */
-int mplb_batch_uses_fused(const mplb_batch *b);
 
 /* Autotuner: time `steps` batch steps (after one warm-up step) for each
  * candidate block shape (candidates = ncand triples bx, by, bz; NULL = a
@@ -285,9 +312,11 @@ int mplb_batch_tune_block(mplb_batch *b, int32_t steps, const int32_t *candidate
                           int32_t best[3], double *best_ms_per_step);
 
 /* Attach an initialised solver for the next nsteps batch steps; *slot
- * receives its slot.  The solver must not step on its own while attached.
- * Errors: EINVAL (dimension/storage/stream mismatch), ENOMEM (no free slot
- * or tile list full), ESTATE (solver not initialised or already attached). */
+ * receives its slot (and its status flag is cleared).  The solver must not
+ * step, be re-initialised or loaded on its own while attached (those calls
+ * return ESTATE).  Errors: EINVAL (dimension/storage/stream mismatch),
+ * ENOMEM (no free slot or tile list full), ESTATE (solver not initialised
+ * or already attached). */
 int mplb_batch_attach(mplb_batch *b, mplb_solver *s, int64_t nsteps, int32_t *slot);
 
 /* Detach the solver in `slot` (its state stays valid and readable). */
@@ -297,8 +326,18 @@ int mplb_batch_detach(mplb_batch *b, int32_t slot);
  * window covers a step is advanced by it. */
 int mplb_batch_step(mplb_batch *b, int64_t nsteps);
 
-/* Steps the solver in `slot` still has to take (0 = finished). */
+/* Steps the solver in `slot` still has to take (0 = finished or retired). */
 int mplb_batch_remaining(const mplb_batch *b, int32_t slot, int64_t *remaining);
+
+/* Health of every slot, status[capacity]: MPLB_OK for an attached solver
+ * whose order parameter has stayed finite, MPLB_EUNSTABLE for one whose
+ * order parameter held a non-finite value at some batch step (checked by
+ * the batch's phi stage at every step, inside the captured graph; a
+ * non-finite population of either set reaches phi within a step),
+ * MPLB_ESTATE for an empty slot.  An unstable solver is retired by this call:
+ * its window closes, so it takes no further batch steps; detach it to free
+ * the slot.  Synchronises the batch stream.  Errors: EINVAL, EDEVICE. */
+int mplb_batch_status(mplb_batch *b, int32_t *status);
 
 /* Batch steps taken so far. */
 int64_t mplb_batch_steps_done(const mplb_batch *b);

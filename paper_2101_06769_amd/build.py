@@ -1,6 +1,4 @@
-"""Build libmplb.so (HIP, gfx950) in-tree with hipcc, and the standalone
-streaming-ceiling probe (stream_probe, an executable that prints the rates
-a kernel without arithmetic reaches on the update's access pattern).
+"""Build libmplb.so (HIP, gfx950) in-tree with hipcc.
 
     python -m paper_2101_06769_amd.build
 """
@@ -16,7 +14,6 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmplb.so")
 SOURCES = ["kernels.hip", "api.cpp"]
-PROBE = os.path.join(HERE, "stream_probe")
 
 # hipcc flags: gfx950 only, C++20, no packed-FP32 instructions, and
 # multiply-add fusion only within one source expression (-ffp-contract=on):
@@ -48,10 +45,20 @@ def _compile(args, target, verbose):
 
 
 def build(verbose: bool = False) -> str:
-    _compile(HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include")] +
-             [os.path.join(CSRC, s) for s in SOURCES], LIB, verbose)
-    probe_flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")]
-    _compile(probe_flags + [os.path.join(CSRC, "stream_probe.hip")], PROBE, verbose)
+    """Compile every source to an object in parallel, then link the library."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    inc = ["-I", os.path.join(ROOT, "include")]
+    cflags = [f for f in HIPCC_FLAGS if f != "-shared"] + inc + ["-c"]
+    objs = [os.path.join(CSRC, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    with ThreadPoolExecutor(len(SOURCES)) as ex:
+        jobs = [ex.submit(_compile, cflags + ["-x", "hip", os.path.join(CSRC, s)], o, verbose)
+                for s, o in zip(SOURCES, objs)]
+        for j in jobs:
+            j.result()
+    _compile(["--offload-arch=gfx950", "-shared", "-fPIC", "--hip-link"] + objs, LIB, verbose)
+    for o in objs:
+        os.remove(o)
     return LIB
 
 

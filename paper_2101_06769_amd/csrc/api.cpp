@@ -45,12 +45,18 @@ constexpr int RED_PARTIALS = 1024;
 
 size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// A byte range of the arena.
+struct Region {
+    size_t off, bytes;
+};
+
 struct Layout {
     int Q;
     long long N, np;
     size_t sF, sG, sT;
     size_t F[2], G[2], phi, fp[2], fr[2], gp[2], phiu[2], npart, nedge, partials, result, total;
     size_t staging_bytes;
+    size_t bF, bG;  // bytes of one population set of each kind (rounded to ALIGN)
 };
 
 bool validate(const mplb_params *p, std::string &why)
@@ -112,6 +118,8 @@ Layout make_layout(const mplb_params *p)
         off += bG;
     }
     L.staging_bytes = bF + bG;
+    L.bF = bF;
+    L.bG = bG;
     L.phi = off;
     off += up(L.np * L.sT, ALIGN);
     const size_t bref = up(L.np * 4, ALIGN);
@@ -204,20 +212,15 @@ struct mplb_solver {
     bool ready;
     bool attached;
     bool hist;  // (phi u) of the previous step is stored (first-order phase-field equilibrium)
-    int fuse;  // one-launch step: 0 never, 1 where faster (at present nowhere), 2 where it applies
     int nphi;  // update kernel that sums the next phi: 0 never, 1 where it applies
     bool nphi_valid;  // the last update wrote partial sums of the current phi
     dim3 block;
     mplb::PhysD ph;
 
     void *at(size_t off) const { return off ? base + off : nullptr; }
-    bool use_fused(const mplb::Ctx &c) const
-    {
-        return fuse != 0 && mplb::fused_ok(c) && (fuse == 2 || mplb::fused_preferred(prm.storage));
-    }
     bool use_nphi(const mplb::Ctx &c) const
     {
-        return nphi != 0 && L.npart != 0 && !use_fused(c) && mplb::nphi_ok(c);
+        return nphi != 0 && L.npart != 0 && mplb::nphi_ok(c);
     }
     mplb::NextPhi next_phi() const
     {
@@ -274,6 +277,26 @@ struct mplb_solver {
         return c;
     }
 
+    // Device regions a step from the current state reads (see save / load).
+    std::vector<Region> state_regions() const
+    {
+        std::vector<Region> r;
+        const int k = cur;
+        r.push_back({L.F[k], L.bF});
+        r.push_back({L.G[k], L.bG});
+        const size_t ref = up(L.np * 4, ALIGN);
+        if (L.fp[k]) r.push_back({L.fp[k], ref});
+        if (L.fr[k]) r.push_back({L.fr[k], ref});
+        if (L.gp[k]) r.push_back({L.gp[k], ref});
+        if (L.phiu[k]) r.push_back({L.phiu[k], size_t(3) * L.np * L.sT});
+        if (nphi_valid) {
+            r.push_back({L.npart, size_t(3) * L.np * L.sT});
+            const mplb::NextPhi q = next_phi();
+            r.push_back({L.nedge, size_t(6) * (prm.n[1] / q.by) * prm.n[2] * prm.n[0] * L.sT});
+        }
+        return r;
+    }
+
     // Context that writes (in place) into buffer k.
     mplb::Ctx ctx_write(int k) const
     {
@@ -281,6 +304,51 @@ struct mplb_solver {
         return c;
     }
 };
+
+namespace {
+
+// ------------------------------------------------------------ save / load
+// A saved state is a host blob: a header (format, parameters, the handle's
+// step bookkeeping and launch settings), a table of region sizes, then the
+// raw device bytes of every region a following step reads: the population
+// buffers of the current level (as stored, FP16 codes included), the
+// per-cell references of the shifted formats, the (phi u) history of the
+// first-order phase-field equilibrium, and the partial sums of phi when the
+// last update wrote them.  Loading them back into a solver with equal
+// parameters reproduces the saved solver's later steps bit for bit.
+constexpr char SAVE_MAGIC[8] = {'M', 'P', 'L', 'B', 'S', 'A', 'V', 'E'};
+constexpr uint32_t SAVE_FORMAT = 1;
+constexpr int SAVE_MAX_REGIONS = 16;
+
+struct SaveHeader {
+    char magic[8];
+    uint32_t format, nregions;
+    uint64_t param_hash;
+    int64_t steps;
+    int32_t cur, hist, nphi, nphi_valid, ready;
+    int32_t block[3];
+};
+
+// FNV-1a over the parameter values (not the struct's padding bytes).
+uint64_t param_hash(const mplb_params &p)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *v, size_t n) {
+        const unsigned char *c = static_cast<const unsigned char *>(v);
+        for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    };
+    mix(&p.dim, 4);
+    mix(p.n, 12);
+    mix(p.bc, 12);
+    const double d[] = {p.rho_heavy, p.rho_light, p.nu_heavy, p.nu_light, p.W, p.mobility,
+                        p.sigma, p.gravity[0], p.gravity[1], p.gravity[2]};
+    mix(d, sizeof(d));
+    const int32_t k[] = {p.storage, p.visc_interp, p.collision, p.cac_edf};
+    mix(k, sizeof(k));
+    return h;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -325,7 +393,6 @@ int mplb_create(const mplb_params *p, void *dev_arena, size_t arena_bytes, void 
     s->ready = false;
     s->attached = false;
     s->block = default_block(p);
-    s->fuse = 1;
     s->nphi = 1;
     s->nphi_valid = false;
     s->ph = make_phys(p);
@@ -344,6 +411,7 @@ int mplb_tune_block(mplb_solver *s, int32_t steps, const int32_t *candidates, in
                                        16, 16, 1, 128, 1, 1};
     if (!s || !best || !best_ms_per_step) return fail(MPLB_EINVAL, "solver and outputs are required");
     if (steps < 1) return fail(MPLB_EINVAL, "steps must be >= 1");
+    if (s->attached) return fail(MPLB_ESTATE, "solver is attached to a batch");
     if (!candidates) {
         candidates = s->prm.dim == 3 ? builtin3 : builtin2;
         ncand = s->prm.dim == 3 ? int32_t(sizeof(builtin3) / 12) : int32_t(sizeof(builtin2) / 12);
@@ -378,23 +446,10 @@ int mplb_tune_block(mplb_solver *s, int32_t steps, const int32_t *candidates, in
     return MPLB_OK;
 }
 
-int mplb_set_fused(mplb_solver *s, int32_t mode)
-{
-    if (!s) return fail(MPLB_EINVAL, "solver is NULL");
-    if (mode < 0 || mode > 2) return fail(MPLB_EINVAL, "mode must be 0, 1 or 2");
-    s->fuse = mode;
-    return MPLB_OK;
-}
-
-int mplb_uses_fused(const mplb_solver *s)
-{
-    if (!s) return fail(MPLB_EINVAL, "solver is NULL");
-    return s->use_fused(s->ctx(s->cur)) ? 1 : 0;
-}
-
 int mplb_set_phi_partials(mplb_solver *s, int32_t mode)
 {
     if (!s) return fail(MPLB_EINVAL, "solver is NULL");
+    if (s->attached) return fail(MPLB_ESTATE, "solver is attached to a batch");
     if (mode != 0 && mode != 1) return fail(MPLB_EINVAL, "mode must be 0 or 1");
     s->nphi = mode;
     return MPLB_OK;
@@ -423,6 +478,7 @@ int mplb_set_block(mplb_solver *s, int32_t bx, int32_t by, int32_t bz)
 int mplb_init(mplb_solver *s, const double *phi, const double *u, const double *p)
 {
     if (!s || !phi || !u) return fail(MPLB_EINVAL, "solver, phi and u are required");
+    if (s->attached) return fail(MPLB_ESTATE, "solver is attached to a batch");
     const long long N = s->L.N;
     const size_t nb = N * sizeof(double);
     // inputs staged as FP64 in buffer 1: phi, u (dim components), p
@@ -454,13 +510,8 @@ int mplb_step(mplb_solver *s, int64_t nsteps)
     if (s->attached) return fail(MPLB_ESTATE, "solver is attached to a batch");
     for (int64_t i = 0; i < nsteps; ++i) {
         const mplb::Ctx c = s->ctx(s->cur);
-        if (s->use_fused(c)) {
-            s->nphi_valid = false;
-            HIPCHK(mplb::launch_step_fused(c));
-        } else {
-            HIPCHK(s->launch_phi_stage(c));
-            HIPCHK(s->launch_update_stage(c));
-        }
+        HIPCHK(s->launch_phi_stage(c));
+        HIPCHK(s->launch_update_stage(c));
         s->cur ^= 1;
         s->steps++;
         s->hist = true;
@@ -473,6 +524,7 @@ int mplb_step_timed(mplb_solver *s, int64_t nsteps, double *ms_phi, double *ms_c
     if (!s || !ms_phi || !ms_collide) return fail(MPLB_EINVAL, "solver and outputs are required");
     if (nsteps < 0) return fail(MPLB_EINVAL, "nsteps must be >= 0");
     if (!s->ready) return fail(MPLB_ESTATE, "mplb_init has not been called");
+    if (s->attached) return fail(MPLB_ESTATE, "solver is attached to a batch");
     constexpr int BATCH = 64;
     hipEvent_t ev[2 * BATCH + 1];
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
@@ -483,11 +535,9 @@ int mplb_step_timed(mplb_solver *s, int64_t nsteps, double *ms_phi, double *ms_c
         hipError_t e = hipEventRecord(ev[0], s->stream);
         for (int i = 0; i < k && e == hipSuccess; ++i) {
             const mplb::Ctx c = s->ctx(s->cur);
-            const bool fused = s->use_fused(c);
-            if (fused) s->nphi_valid = false;
-            e = fused ? hipSuccess : s->launch_phi_stage(c);
+            e = s->launch_phi_stage(c);
             if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 1], s->stream);
-            if (e == hipSuccess) e = fused ? mplb::launch_step_fused(c) : s->launch_update_stage(c);
+            if (e == hipSuccess) e = s->launch_update_stage(c);
             if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 2], s->stream);
             s->cur ^= 1;
             s->steps++;
@@ -577,6 +627,7 @@ int mplb_set_populations(mplb_solver *s, int32_t which, const double *host_in)
 {
     if (!s || !host_in) return fail(MPLB_EINVAL, "solver and host_in are required");
     if (which != 0 && which != 1) return fail(MPLB_EINVAL, "which must be 0 (f') or 1 (g)");
+    if (s->attached) return fail(MPLB_ESTATE, "solver is attached to a batch");
     const bool shifted = which == 0 ? s->L.sF == 2 : s->L.sG == 2;
     if (shifted && !s->ready)
         return fail(MPLB_ESTATE, "FP16-shifted sets keep the shift/scale of the current state: "
@@ -600,6 +651,98 @@ int mplb_set_populations(mplb_solver *s, int32_t which, const double *host_in)
     return MPLB_OK;
 }
 
+size_t mplb_save_bytes(const mplb_solver *s)
+{
+    if (!s) return 0;
+    size_t n = sizeof(SaveHeader) + sizeof(mplb_params) + SAVE_MAX_REGIONS * sizeof(uint64_t);
+    for (const Region &r : s->state_regions()) n += r.bytes;
+    return n;
+}
+
+int mplb_save(mplb_solver *s, void *host_blob, size_t bytes)
+{
+    if (!s || !host_blob) return fail(MPLB_EINVAL, "solver and blob are required");
+    if (!s->ready) return fail(MPLB_ESTATE, "mplb_init has not been called");
+    const size_t need = mplb_save_bytes(s);
+    if (bytes < need)
+        return fail(MPLB_EINVAL, "blob holds " + std::to_string(bytes) + " bytes, " +
+                                     std::to_string(need) + " needed");
+    const std::vector<Region> reg = s->state_regions();
+    char *out = static_cast<char *>(host_blob);
+    SaveHeader h{};
+    std::memcpy(h.magic, SAVE_MAGIC, 8);
+    h.format = SAVE_FORMAT;
+    h.nregions = uint32_t(reg.size());
+    h.param_hash = param_hash(s->prm);
+    h.steps = s->steps;
+    h.cur = s->cur;
+    h.hist = s->hist;
+    h.nphi = s->nphi;
+    h.nphi_valid = s->nphi_valid;
+    h.ready = s->ready;
+    h.block[0] = int32_t(s->block.x);
+    h.block[1] = int32_t(s->block.y);
+    h.block[2] = int32_t(s->block.z);
+    std::memcpy(out, &h, sizeof(h));
+    std::memcpy(out + sizeof(h), &s->prm, sizeof(mplb_params));
+    uint64_t sizes[SAVE_MAX_REGIONS] = {};
+    for (size_t i = 0; i < reg.size(); ++i) sizes[i] = reg[i].bytes;
+    std::memcpy(out + sizeof(h) + sizeof(mplb_params), sizes, sizeof(sizes));
+    char *pos = out + sizeof(h) + sizeof(mplb_params) + sizeof(sizes);
+    for (const Region &r : reg) {
+        HIPCHK(hipMemcpyAsync(pos, s->base + r.off, r.bytes, hipMemcpyDeviceToHost, s->stream));
+        pos += r.bytes;
+    }
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return MPLB_OK;
+}
+
+int mplb_load(mplb_solver *s, const void *host_blob, size_t bytes)
+{
+    if (!s || !host_blob) return fail(MPLB_EINVAL, "solver and blob are required");
+    if (s->attached) return fail(MPLB_ESTATE, "solver is attached to a batch");
+    const char *in = static_cast<const char *>(host_blob);
+    constexpr size_t head = sizeof(SaveHeader) + sizeof(mplb_params) + SAVE_MAX_REGIONS * sizeof(uint64_t);
+    if (bytes < head) return fail(MPLB_EINVAL, "blob is shorter than its header");
+    SaveHeader h;
+    std::memcpy(&h, in, sizeof(h));
+    if (std::memcmp(h.magic, SAVE_MAGIC, 8) != 0 || h.format != SAVE_FORMAT)
+        return fail(MPLB_EINVAL, "not a saved state of this library version");
+    if (h.param_hash != param_hash(s->prm))
+        return fail(MPLB_EINVAL, "saved state belongs to other parameters");
+    if (h.nregions > SAVE_MAX_REGIONS || (h.cur != 0 && h.cur != 1) || h.steps < 0)
+        return fail(MPLB_EINVAL, "corrupt saved state header");
+    uint64_t sizes[SAVE_MAX_REGIONS];
+    std::memcpy(sizes, in + sizeof(h) + sizeof(mplb_params), sizeof(sizes));
+    // the regions the saved bookkeeping implies, on this solver's layout
+    mplb_solver probe = *s;
+    probe.cur = h.cur;
+    probe.nphi = h.nphi;
+    probe.nphi_valid = h.nphi_valid != 0;
+    const std::vector<Region> reg = probe.state_regions();
+    size_t total = head;
+    if (reg.size() != h.nregions) return fail(MPLB_EINVAL, "saved state does not match the layout");
+    for (size_t i = 0; i < reg.size(); ++i) {
+        if (sizes[i] != reg[i].bytes) return fail(MPLB_EINVAL, "saved state does not match the layout");
+        total += reg[i].bytes;
+    }
+    if (bytes < total) return fail(MPLB_EINVAL, "blob is truncated");
+    const char *pos = in + head;
+    for (const Region &r : reg) {
+        HIPCHK(hipMemcpyAsync(s->base + r.off, pos, r.bytes, hipMemcpyHostToDevice, s->stream));
+        pos += r.bytes;
+    }
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->cur = h.cur;
+    s->steps = h.steps;
+    s->hist = h.hist != 0;
+    s->nphi = h.nphi;
+    s->nphi_valid = h.nphi_valid != 0;
+    s->ready = h.ready != 0;
+    s->block = dim3(h.block[0], h.block[1], h.block[2]);
+    return MPLB_OK;
+}
+
 
 }  // extern "C"
 
@@ -613,6 +756,7 @@ struct mplb_batch {
     mplb::BatchTile *d_tiles;
     int *d_ntiles;
     long long *d_tbase;
+    int *d_status;  // per slot: non-zero once the phi stage met a non-finite value
     std::vector<mplb_solver *> slot;
     std::vector<mplb::BatchDom> doms;
     std::vector<mplb::BatchTile> tiles;
@@ -628,8 +772,6 @@ struct mplb_batch {
     dim3 block;
     int chunk;
     bool row;     // row-form kernels (see row_form_ok)
-    int fuse;     // one-launch step: 0 never, 1 where faster (at present nowhere), 2 where allowed
-    bool fused;   // one-launch step over fused tiles
     long long t;  // batch steps taken
     hipGraphExec_t exec;
     bool have_graph;
@@ -638,7 +780,7 @@ struct mplb_batch {
 namespace {
 
 size_t table_layout(int32_t capacity, int64_t max_tiles, size_t *o_doms, size_t *o_tiles,
-                    size_t *o_nt, size_t *o_tb)
+                    size_t *o_nt, size_t *o_tb, size_t *o_st)
 {
     size_t off = 0;
     *o_doms = off;
@@ -649,6 +791,8 @@ size_t table_layout(int32_t capacity, int64_t max_tiles, size_t *o_doms, size_t 
     off += ALIGN;
     *o_tb = off;
     off += ALIGN;
+    *o_st = off;
+    off += up(sizeof(int) * capacity, ALIGN);
     return off;
 }
 
@@ -663,18 +807,14 @@ void drop_graph(mplb_batch *b)
 int upload_tables(mplb_batch *b)
 {
     b->tiles.clear();
-    bool fused = b->fuse == 2 || (b->fuse == 1 && mplb::fused_preferred(b->storage));
-    for (int i = 0; i < b->capacity; ++i)
-        if (b->slot[i])
-            fused = fused && mplb::fused_ok_geom(b->dim, b->collision & 1, b->doms[i].g);
     // domains whose update sums the next phi, as their solver's own step
-    // would (not with the one-launch step)
+    // would
     for (int i = 0; i < b->capacity; ++i) {
         mplb_solver *s = b->slot[i];
         if (!s) continue;
         mplb::BatchDom &d = b->doms[i];
         const mplb::Ctx c = s->ctx(s->cur);
-        const int by = (!fused && b->dim == 3 && s->use_nphi(c)) ? s->next_phi().by : 0;
+        const int by = (b->dim == 3 && s->use_nphi(c)) ? s->next_phi().by : 0;
         if (by != d.nphi_by) {
             d.nphi_by = by;
             d.nphi_from = b->t + 1;  // no partial sums of the current phi yet
@@ -701,16 +841,6 @@ int upload_tables(mplb_batch *b)
             if (!s) continue;
             const int nx = s->prm.n[0], ny = s->prm.n[1], nz = s->prm.n[2];
             const int nby = b->doms[i].nphi_by;
-            if (fused) {
-                if (pass != 0) continue;
-                // whole rows, chunks of 32 planes
-                const int rows = mplb::fused_rows(nx), zc = 32;
-                for (int y0 = 0; y0 < ny; y0 += rows)
-                    for (int z0 = 0; z0 < nz; z0 += zc)
-                        if (!push(mplb::BatchTile{i, 0, y0, z0, z0 + zc < nz ? z0 + zc : nz, 0}))
-                            return fail(MPLB_ENOMEM, "batch tile list is full");
-                continue;
-            }
             if (pass >= 2) {
                 // one group per row length (nphi_group)
                 if (!nby || nx != mplb::nphi_group_width(pass - 2)) continue;
@@ -746,8 +876,6 @@ int upload_tables(mplb_batch *b)
             seg[2] += wcount[pass - 2];
         }
     }
-    if (fused != b->fused) drop_graph(b);
-    b->fused = fused;
     b->ntiles_host = seg[0];
     b->ntiles_phi_host = seg[0] + seg[1];
     b->ntiles_nphi_host = seg[2];
@@ -791,8 +919,8 @@ extern "C" {
 size_t mplb_batch_table_bytes(int32_t capacity, int64_t max_tiles)
 {
     if (capacity < 1 || max_tiles < 1) return 0;
-    size_t a, b, c, d;
-    return table_layout(capacity, max_tiles, &a, &b, &c, &d);
+    size_t a, b, c, d, e;
+    return table_layout(capacity, max_tiles, &a, &b, &c, &d, &e);
 }
 
 int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t max_tiles,
@@ -809,8 +937,8 @@ int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t ma
         return fail(MPLB_EINVAL, "table memory must be non-NULL and 256-byte aligned");
     if (!hip_stream)
         return fail(MPLB_EINVAL, "a batch needs its own stream (graphs cannot capture the null stream)");
-    size_t od, ot, on, ob;
-    const size_t need = table_layout(capacity, max_tiles, &od, &ot, &on, &ob);
+    size_t od, ot, on, ob, os;
+    const size_t need = table_layout(capacity, max_tiles, &od, &ot, &on, &ob, &os);
     if (table_bytes < need) return fail(MPLB_ENOMEM, "batch table memory too small");
     mplb_batch *b = new (std::nothrow) mplb_batch();
     if (!b) return fail(MPLB_ENOMEM, "host allocation failed");
@@ -825,6 +953,7 @@ int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t ma
     b->d_tiles = reinterpret_cast<mplb::BatchTile *>(base + ot);
     b->d_ntiles = reinterpret_cast<int *>(base + on);
     b->d_tbase = reinterpret_cast<long long *>(base + ob);
+    b->d_status = reinterpret_cast<int *>(base + os);
     b->slot.assign(capacity, nullptr);
     b->doms.assign(capacity, mplb::BatchDom{});
     b->ntiles_host = b->ntiles_phi_host = b->ntiles_nphi_host = 0;
@@ -836,9 +965,11 @@ int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t ma
     b->t = 0;
     b->have_graph = false;
     b->row = true;
-    b->fuse = 1;
-    b->fused = false;
-    const int rc = upload_tables(b);
+    int rc = upload_tables(b);
+    if (rc == MPLB_OK && mplb::launch_fill_i32(b->d_status, capacity, 0, b->stream) != hipSuccess)
+        rc = fail(MPLB_EDEVICE, "clearing the batch status flags failed");
+    if (rc == MPLB_OK && hipStreamSynchronize(b->stream) != hipSuccess)
+        rc = fail(MPLB_EDEVICE, "hipStreamSynchronize failed");
     if (rc != MPLB_OK) {
         delete b;
         return rc;
@@ -856,20 +987,6 @@ int mplb_batch_set_block(mplb_batch *b, int32_t bx, int32_t by, int32_t bz)
     b->block = dim3(bx, by, bz);
     drop_graph(b);
     return upload_tables(b);
-}
-
-int mplb_batch_set_fused(mplb_batch *b, int32_t mode)
-{
-    if (!b) return fail(MPLB_EINVAL, "batch is NULL");
-    if (mode < 0 || mode > 2) return fail(MPLB_EINVAL, "mode must be 0, 1 or 2");
-    b->fuse = mode;
-    return upload_tables(b);
-}
-
-int mplb_batch_uses_fused(const mplb_batch *b)
-{
-    if (!b) return fail(MPLB_EINVAL, "batch is NULL");
-    return b->fused ? 1 : 0;
 }
 
 int mplb_batch_set_graph_chunk(mplb_batch *b, int32_t chunk)
@@ -934,6 +1051,7 @@ int mplb_batch_attach(mplb_batch *b, mplb_solver *s, int64_t nsteps, int32_t *sl
     b->slot[k] = s;
     b->doms[k] = d;
     s->attached = true;
+    HIPCHK(mplb::launch_fill_i32(b->d_status + k, 1, 0, b->stream));
     const int rc = upload_tables(b);
     if (rc != MPLB_OK) {
         b->slot[k] = nullptr;
@@ -967,6 +1085,29 @@ int mplb_batch_remaining(const mplb_batch *b, int32_t slot, int64_t *remaining)
 
 int64_t mplb_batch_steps_done(const mplb_batch *b) { return b ? b->t : -1; }
 
+int mplb_batch_status(mplb_batch *b, int32_t *status)
+{
+    if (!b || !status) return fail(MPLB_EINVAL, "batch and status are required");
+    std::vector<int> flags(b->capacity);
+    HIPCHK(hipMemcpyAsync(flags.data(), b->d_status, sizeof(int) * b->capacity,
+                          hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    bool closed = false;
+    for (int i = 0; i < b->capacity; ++i) {
+        if (!b->slot[i]) {
+            status[i] = MPLB_ESTATE;
+            continue;
+        }
+        status[i] = flags[i] ? MPLB_EUNSTABLE : MPLB_OK;
+        if (flags[i] && b->doms[i].last > b->t) {
+            // retire: the slot takes no further batch steps
+            b->doms[i].last = b->t;
+            closed = true;
+        }
+    }
+    return closed ? upload_tables(b) : MPLB_OK;
+}
+
 int mplb_batch_step(mplb_batch *b, int64_t nsteps)
 {
     if (!b) return fail(MPLB_EINVAL, "batch is NULL");
@@ -983,8 +1124,8 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
                 hipError_t e = hipSuccess;
                 for (int k = 0; k < b->chunk && e == hipSuccess; ++k)
                     e = mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row,
-                                                b->fused, b->d_doms, b->d_tiles, b->d_ntiles,
-                                                b->d_tbase, k, b->block, b->grid, b->stream);
+                                                b->d_doms, b->d_tiles, b->d_ntiles, b->d_tbase, k,
+                                                b->block, b->grid, b->d_status, b->stream);
                 // always end the capture, so that a failure leaves the stream usable
                 const hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
                 if (e != hipSuccess || e2 != hipSuccess) {
@@ -1002,9 +1143,9 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
             b->t += b->chunk;
             done += b->chunk;
         } else {
-            HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row, b->fused,
-                                           b->d_doms, b->d_tiles, b->d_ntiles, b->d_tbase, 0,
-                                           b->block, b->grid, b->stream));
+            HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row, b->d_doms,
+                                           b->d_tiles, b->d_ntiles, b->d_tbase, 0, b->block,
+                                           b->grid, b->d_status, b->stream));
             b->t += 1;
             done += 1;
         }

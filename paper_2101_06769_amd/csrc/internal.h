@@ -85,17 +85,6 @@ constexpr int nphi_group(int nx) { return nx == 512 ? 4 : nx / 64 - 1; }
 hipError_t launch_collide_nphi(const Ctx &c, const NextPhi &q);
 // phi of the current level from the partial sums of the previous update.
 hipError_t launch_phi_merge(const Ctx &c, const NextPhi &q);
-// One-launch step (phi into LDS, then the collision) for 3-D cumulant
-// lattices periodic in x with nx <= 256 and arrays of fewer than 2^31
-// elements; fused_ok tells whether it applies.  It does not write the phi
-// array (launch_phi refreshes it for readers).
-bool fused_ok(const Ctx &c);
-bool fused_ok_geom(int dim, int collision, const Geom &g);
-// Storage formats for which the fused step is the faster one (none at present).
-bool fused_preferred(int storage);
-// Rows per tile of the fused kernel for rows of nx cells (512 threads).
-int fused_rows(int nx);
-hipError_t launch_step_fused(const Ctx &c);
 // Equilibrium initial state from device FP64 fields (phi[N], u[dim][N], p[N])
 // written into the Fout/Gout buffers in pull layout.
 hipError_t launch_init(const Ctx &c, const double *phi, const double *u, const double *pr);
@@ -133,8 +122,7 @@ struct BatchDom {
 
 // A tile of a batch: domain index, origin cell (x0, y0, z0), end of its
 // plane range z1 and width w: w cells in x by (threads per block) / w rows,
-// one plane; for the fused kernels whole rows y0 .. y0 + rows - 1 over
-// planes z0 .. z1 - 1 (w unused).
+// one plane.
 struct BatchTile {
     int dom, x0, y0, z0, z1, w;
 };
@@ -145,11 +133,10 @@ bool row_form_ok(int dim, const Geom &g, dim3 block);
 // row: every attached domain satisfies row_form_ok with this block.
 // One batch step over the tile list (*ntiles entries), batch step index
 // *tbase + step_off.  collision: operator code, bit 0 the flow collision, bit
-// 1 the first-order phase-field equilibrium (shared by all domains).  fused:
-// one kernel per step over fused tiles (every attached domain satisfies
-// fused_ok_geom); else the phi pass and the update over block tiles (row:
-// every domain takes the row form).  grid blocks stride over the tiles (at
-// least one per tile: hardware scheduling).
+// 1 the first-order phase-field equilibrium (shared by all domains).  The
+// phi pass and the update run over block tiles (row: every domain takes the
+// row form).  grid blocks stride over the tiles (at least one per tile:
+// hardware scheduling).
 // Tile list: ntiles[0] block tiles of the domains the block kernels update,
 // then block tiles of the phi-summing domains up to ntiles[1] (their phi
 // stage merges partial sums), then the tiles of the phi-summing update
@@ -157,12 +144,16 @@ bool row_form_ok(int dim, const Geom &g, dim3 block);
 // (nphi_group): group k starts at ntiles[2 + 2k] and holds ntiles[3 + 2k]
 // tiles.  grid[0], grid[1]: blocks of the phi stage and the update;
 // grid[2 + k]: of group k's update (0: not launched); 2 + NPHI_GROUPS entries.
-hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool fused,
+// status[dom] is or-ed with 1 when the phi stage finds a non-finite order
+// parameter in that domain.
+hipError_t launch_batch_step(int dim, int storage, int collision, bool row,
                              const BatchDom *doms, const BatchTile *tiles, const int *ntiles,
                              const long long *tbase, int step_off, dim3 block, const int *grid,
-                             hipStream_t stream);
+                             int *status, hipStream_t stream);
 // Threads per block of the phi-summing update for a storage format.
 int nphi_block_threads(int storage);
 hipError_t launch_set_i64(long long *ptr, long long v, hipStream_t stream);
+// ptr[0 .. n) = v by a kernel (no memset node when captured into a graph).
+hipError_t launch_fill_i32(int *ptr, int n, int v, hipStream_t stream);
 
 }  // namespace mplb

@@ -12,10 +12,9 @@
 //              stored at the cell (pull streaming: the next step gathers);
 // or, where the lattice allows it, k_phi_merge (phi from partial sums) and
 // k_collide_nphi (the same update, which also sums the next phi from the
-// values it stores; see "next order parameter" below); or one launch,
-// k_fused, that keeps phi in LDS (see "fused step" below).  The batched forms
-// (kb_step, kb_collide_nphi, kb_fused) run the same per-cell bodies over a
-// tile list of many independent domains.
+// values it stores; see "next order parameter" below).  The batched forms
+// (kb_step, kb_collide_nphi) run the same per-cell bodies over a tile list of
+// many independent domains.
 //
 // Flow collision.  All cumulant rates other than the viscous ones are unity
 // (Sec. 2.3), so every post-collision cumulant above second order is zero and
@@ -205,38 +204,6 @@ __device__ __forceinline__ T pull(const NbRow &n, const void *base, long long, i
     }
 }
 
-// Row form with plane, row and column combined into one 32-bit element index
-// per load: more vector address arithmetic, but no scalar base per load.  For
-// kernels at their register limit (the fused step's 512-thread tiles, the
-// FP16 update that also sums phi), where the scalar bases of the split form
-// spill.
-struct NbRowC : NbRow {
-};
-
-__device__ __forceinline__ NbRowC make_nb(const Geom &g, int x, int y, int z, NbRowC *)
-{
-    NbRowC n;
-    static_cast<NbRow &>(n) = make_nb(g, x, y, z, (NbRow *)nullptr);
-    return n;
-}
-
-template <int D, class S, typename T>
-__device__ __forceinline__ T pull(const NbRowC &n, const void *base, long long, int a,
-                                  const float *sh, const float *sc)
-{
-    int dir, rs, xs;
-    row_src<D>(n, a, dir, rs, xs);
-    const unsigned cell = unsigned(rs) + unsigned(xs);
-    const unsigned e = unsigned(dir * n.np) + cell;
-    if constexpr (S::shifted) {
-        const float q = __half2float(static_cast<const __half *>(base)[e]);
-        const float w = weight<D, float>(a);
-        return T(w * (sh[cell] + (sc ? sc[cell] : 1.0f) * q));
-    } else {
-        return T(static_cast<const typename S::raw *>(base)[e]);
-    }
-}
-
 // phi at the stencil neighbour (x + cx, y + cy, z + cz): periodic wrap, or the
 // mirrored first fluid layer beyond walls and symmetry planes.
 template <typename T>
@@ -254,13 +221,6 @@ __device__ __forceinline__ T phi_at(const NbRow &n, const T *phi, int cx, int cy
 {
     const int xx = cx == 0 ? n.x : cx > 0 ? n.xp : n.xm;
     return *lane_ptr(phi, (long long)(n.ry[1 + cy] + n.rz[1 + cz]), xx);
-}
-
-template <typename T>
-__device__ __forceinline__ T phi_at(const NbRowC &n, const T *phi, int cx, int cy, int cz)
-{
-    const int xx = cx == 0 ? n.x : cx > 0 ? n.xp : n.xm;
-    return phi[unsigned(n.ry[1 + cy] + n.rz[1 + cz]) + unsigned(xx)];
 }
 
 // Parameters in the arithmetic type.
@@ -554,7 +514,7 @@ __device__ __forceinline__ T source_xi(const Cell<T> &c, int a, T usq, T V, T &g
 
 // ------------------------------------------------------------------ kernels
 
-// Occupancy target of the fused collision: four wavefronts per SIMD for the
+// Occupancy target of the cell update: four wavefronts per SIMD for the
 // D3Q27 kernels with FP32 arithmetic and plain FP32 flow storage (at most 128
 // VGPRs: measured faster than five, which spills, and than no cap); the
 // compiler's choice otherwise (the FP16 formats gather a shift and a scale
@@ -567,7 +527,7 @@ constexpr int collide_waves()
 
 // phi(x) = sum_a g_a(x) over the pulled phase-field populations (Sec. 2.2).
 template <int D, class P, class NB>
-__device__ __forceinline__ void phi_body(const NB &nb, long long np, const Ptrs &p)
+__device__ __forceinline__ typename P::T phi_body(const NB &nb, long long np, const Ptrs &p)
 {
     using T = typename P::T;
     constexpr int Q = Lat<D>::Q;
@@ -575,20 +535,21 @@ __device__ __forceinline__ void phi_body(const NB &nb, long long np, const Ptrs 
 #pragma unroll
     for (int a = 0; a < Q; ++a) s += pull<D, typename P::G, T>(nb, p.Gin, np, a, p.gp_in, nullptr);
     __builtin_nontemporal_store(s, lane_ptr(static_cast<T *>(p.phi), nb.row, nb.x));  // read a launch later
+    return s;
 }
 
 // x per lane; y and z wavefront-uniform when NB is NbRow.
 template <int D, class P, class NB>
-__device__ __forceinline__ void phi_cell(const Geom &g, const Ptrs &p, int x, int y, int z)
+__device__ __forceinline__ typename P::T phi_cell(const Geom &g, const Ptrs &p, int x, int y, int z)
 {
     const NB nb = make_nb(g, x, y, z, (NB *)nullptr);
-    phi_body<D, P>(nb, g.np, p);
+    return phi_body<D, P>(nb, g.np, p);
 }
 
 template <int D, class P, bool ROW>
 __global__ void __launch_bounds__(256) k_phi(Geom g, Ptrs p);
 
-// The fused update of one cell: stencil, closure, flow collision, phase-field
+// The update of one cell: stencil, closure, flow collision, phase-field
 // collision; post-collision values stored at the cell.  COLL bit 0: flow
 // collision (0 cumulant, 1 single relaxation time); bit 1: first-order
 // phase-field equilibrium with the correction term.  KEEP: the stored
@@ -1058,7 +1019,7 @@ __global__ void __launch_bounds__(256) k_phi_merge(Geom g, Ptrs p, NextPhi q)
 
 // phi of cell (x, y, z) from its pieces, loaded one by one (batched form).
 template <typename T>
-__device__ __forceinline__ void nphi_merge_cell(const Geom &g, const Ptrs &p, const NextPhi &q,
+__device__ __forceinline__ T nphi_merge_cell(const Geom &g, const Ptrs &p, const NextPhi &q,
                                                 int x, int y, int z)
 {
     const int by = q.by, ntiles = g.ny / by;
@@ -1077,117 +1038,9 @@ __device__ __forceinline__ void nphi_merge_cell(const Geom &g, const Ptrs &p, co
         v[oz + 1][1] = ok && first ? *lane_ptr(edge, nphi_edge_at(g, ntiles, 0, oz, t, z, 0), x) : T(0);
         v[oz + 1][2] = ok && last ? *lane_ptr(edge, nphi_edge_at(g, ntiles, 1, oz, t, z, 0), x) : T(0);
     }
-    __builtin_nontemporal_store(nphi_merge_sum(g, v, z, first, last), lane_ptr(static_cast<T *>(p.phi), row, x));
-}
-
-// ------------------------------------------------------------- fused step
-// One launch per time step for 3-D lattices periodic in x with at most 256
-// cells per row.  A block of 512 threads covers bx-wide rows (bx = 64, 128 or
-// 256 >= nx, so a row and its periodic x-neighbours are all in the block) for
-// by = 512 / bx rows and marches along z over a chunk of planes.  For each
-// plane it first sums the pulled g into the order parameter of its rows and
-// one halo row on either side (Sec. 2.2, zeroth moment), into a ring of three
-// LDS planes, then updates the middle plane with the stencil read from LDS.
-// The pulled g of a cell are read twice (for phi, then for the collision) but
-// the second read finds them in cache, and phi never goes to HBM.
-
-constexpr int FUSED_THREADS = 512;
-constexpr int FUSED_LDS = 3 * FUSED_THREADS * 2;  // three planes of (by + 2) bx <= 1024 cells
-
-__host__ __device__ constexpr int fused_bx(int nx) { return nx <= 64 ? 64 : nx <= 128 ? 128 : 256; }
-
-// Neighbourhood of a cell of the fused kernel: row-form pulls, stencil from
-// the LDS rows of planes z - 1, z, z + 1 (each row `rowlen` long, the cell's
-// own row in the middle of three).
-template <typename T>
-struct NbFused : NbRowC {
-    const T *pl[3];
-    int rowlen;
-};
-
-template <typename T>
-__device__ __forceinline__ T phi_at(const NbFused<T> &n, const T *, int cx, int cy, int cz)
-{
-    const int xx = cx == 0 ? n.x : cx > 0 ? n.xp : n.xm;
-    return n.pl[1 + cz][cy * n.rowlen + xx];
-}
-
-// Coordinate s on an axis of n cells for the halo rows and planes of the
-// fused kernel: wrapped on a periodic axis (any s), else clamped (the ghost
-// layer mirrors the first fluid layer; beyond a partial tile the value is
-// computed but not used).
-__device__ __forceinline__ int halo_coord(int s, int n, int bc)
-{
-    if (bc == BC_PER) return ((s % n) + n) % n;
-    return s < 0 ? 0 : s >= n ? n - 1 : s;
-}
-
-// Planes z0 <= z < z1 of rows y0 .. y0 + by - 1 (whole rows), by one block
-// of FUSED_THREADS threads; sphi is the block's LDS.  Every thread of the
-// block must call it; it ends with a barrier, so sphi may be reused after.
-template <int D, class P, int COLL>
-__device__ __forceinline__ void fused_tile(const Geom &g, const Phys<typename P::T> &ph,
-                                           const Ptrs &p, int y0, int z0, int z1,
-                                           typename P::T *sphi)
-{
-    using T = typename P::T;
-    constexpr int Q = Lat<D>::Q;
-    const int bx = fused_bx(g.nx), by = FUSED_THREADS / bx;
-    const int tid = int(threadIdx.x);
-    const int x = tid & (bx - 1);
-    const int ty = __builtin_amdgcn_readfirstlane(tid / bx);  // one row per wavefront
-    const int psz = (by + 2) * bx;
-    const bool xin = x < g.nx;
-    // phi of plane zz (halo-mapped) for rows y0 - 1 .. y0 + by into LDS slot
-    auto plane = [&](int zz, int slot) {
-        const int zh = halo_coord(zz, g.nz, g.bcz);
-        for (int r = ty; r < by + 2; r += by) {
-            const int yh = halo_coord(y0 - 1 + r, g.ny, g.bcy);
-            if (xin) {
-                const NbRowC nb = make_nb(g, x, yh, zh, (NbRowC *)nullptr);
-                T sum = 0;
-#pragma unroll
-                for (int a = 0; a < Q; ++a)
-                    sum += pull<D, typename P::G, T>(nb, p.Gin, g.np, a, p.gp_in, nullptr);
-                sphi[slot * psz + r * bx + x] = sum;
-            }
-        }
-    };
-    int sm = 0, s0 = 1, sp = 2;  // LDS slots of planes z - 1, z, z + 1
-    plane(z0 - 1, sm);
-    plane(z0, s0);
-    for (int z = z0; z < z1; ++z) {
-        plane(z + 1, sp);
-        __syncthreads();
-        const int y = y0 + ty;
-        if (xin && y < g.ny) {
-            NbFused<T> n;
-            static_cast<NbRowC &>(n) = make_nb(g, x, y, z, (NbRowC *)nullptr);
-            n.pl[0] = sphi + sm * psz + (ty + 1) * bx;
-            n.pl[1] = sphi + s0 * psz + (ty + 1) * bx;
-            n.pl[2] = sphi + sp * psz + (ty + 1) * bx;
-            n.rowlen = bx;
-            collide_body<D, P, COLL>(n, g, ph, p);
-        }
-        __syncthreads();  // the slot of plane z - 1 is overwritten next
-        const int t = sm;
-        sm = s0;
-        s0 = sp;
-        sp = t;
-    }
-}
-
-template <int D, class P, int COLL>
-__global__ void __launch_bounds__(FUSED_THREADS)
-__attribute__((amdgpu_waves_per_eu(collide_waves<D, P, COLL>())))
-k_fused(Geom g, Phys<typename P::T> ph, Ptrs p, int zc)
-{
-    using T = typename P::T;
-    __shared__ T sphi[FUSED_LDS];
-    const int by = FUSED_THREADS / fused_bx(g.nx);
-    const int z0 = int(blockIdx.z) * zc;
-    fused_tile<D, P, COLL>(g, ph, p, int(blockIdx.y) * by, z0, z0 + zc < g.nz ? z0 + zc : g.nz,
-                           sphi);
+    const T s = nphi_merge_sum(g, v, z, first, last);
+    __builtin_nontemporal_store(s, lane_ptr(static_cast<T *>(p.phi), row, x));
+    return s;
 }
 
 // Equilibrium initial state, computed in FP64 for every storage format and
@@ -1426,8 +1279,8 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_final(const double *part
 // a tile list (one block per tile when the launch has a block per tile); each
 // tile names its domain, whose geometry, parameters, buffers and active step
 // window are read from the domain table.  The per-cell arithmetic is the
-// single-domain path's (phi_cell, collide_cell, nphi_merge_sum, nphi_tile,
-// fused_tile), so a domain's result does not depend on the batch it is in.
+// single-domain path's (phi_cell, collide_cell, nphi_merge_sum, nphi_tile),
+// so a domain's result does not depend on the batch it is in.
 
 __device__ __forceinline__ Ptrs batch_ptrs(const BatchDom &d, int in, bool have_prev)
 {
@@ -1454,11 +1307,14 @@ __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(PHI ? 1 : collide_waves<D, P, COLL>()))) kb_step(const BatchDom *__restrict__ doms,
                                                const BatchTile *__restrict__ tiles,
                                                const int *ntiles, const long long *tbase,
-                                               int step_off)
+                                               int step_off, int *status)
 {
     using T = typename P::T;
     const long long t = *tbase + step_off;
-    // the phi stage covers every domain, the update those without nphi_by
+    // the phi stage covers every domain, the update those without nphi_by;
+    // the phi stage also flags a domain whose order parameter is not finite
+    // (status[dom] != 0): a non-finite population of either set reaches phi
+    // within a step
     const int nt = PHI ? ntiles[1] : ntiles[0];
     for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
         const BatchTile tl = tiles[ti];
@@ -1479,11 +1335,11 @@ __attribute__((amdgpu_waves_per_eu(PHI ? 1 : collide_waves<D, P, COLL>()))) kb_s
         if (x >= g.nx || y >= g.ny || z >= tl.z1) continue;
         const int nby = doms[tl.dom].nphi_by;
         if constexpr (PHI) {
-            if (D == 3 && nby && t >= doms[tl.dom].nphi_from)
-                nphi_merge_cell<T>(g, p, NextPhi{doms[tl.dom].npart,
-                                                 doms[tl.dom].nedge, nby}, x, y, z);
-            else
-                phi_cell<D, P, NbOf<ROW>>(g, p, x, y, z);
+            const T ph = (D == 3 && nby && t >= doms[tl.dom].nphi_from)
+                             ? nphi_merge_cell<T>(g, p, NextPhi{doms[tl.dom].npart,
+                                                                doms[tl.dom].nedge, nby}, x, y, z)
+                             : phi_cell<D, P, NbOf<ROW>>(g, p, x, y, z);
+            if (!__builtin_isfinite(ph)) atomicOr(status + tl.dom, 1);
         } else {
             const Phys<T> ph = to_phys<T>(doms[tl.dom].ph);
             collide_cell<D, P, COLL, NbOf<ROW>>(g, ph, p, x, y, z);
@@ -1531,30 +1387,13 @@ kb_collide_nphi(const BatchDom *__restrict__ doms, const BatchTile *__restrict__
     }
 }
 
-// Batched one-launch step: blocks stride over fused tiles (domain, rows
-// y0 .., planes z0 .. z1 - 1), each a fused_tile of its domain.
-template <int D, class P, int COLL>
-__global__ void __launch_bounds__(FUSED_THREADS)
-__attribute__((amdgpu_waves_per_eu(collide_waves<D, P, COLL>())))
-kb_fused(const BatchDom *__restrict__ doms, const BatchTile *__restrict__ tiles, const int *ntiles,
-         const long long *tbase, int step_off)
-{
-    using T = typename P::T;
-    __shared__ T sphi[FUSED_LDS];
-    const long long t = *tbase + step_off;
-    const int nt = *ntiles;
-    for (int ti = blockIdx.x; ti < nt; ti += gridDim.x) {
-        const BatchTile tl = tiles[ti];
-        const Geom g = doms[tl.dom].g;  // by value, see kb_step
-        const long long first = doms[tl.dom].first, last = doms[tl.dom].last;
-        if (t < first || t >= last) continue;
-        const Ptrs p = batch_ptrs(doms[tl.dom], int((t - first) & 1), t >= doms[tl.dom].hist_from);
-        const Phys<T> ph = to_phys<T>(doms[tl.dom].ph);
-        fused_tile<D, P, COLL>(g, ph, p, tl.y0, tl.z0, tl.z1, sphi);
-    }
-}
-
 __global__ void k_set_i64(long long *ptr, long long v) { *ptr = v; }
+
+__global__ void __launch_bounds__(256) k_fill_i32(int *ptr, int n, int v)
+{
+    const int i = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) ptr[i] = v;
+}
 
 // --------------------------------------------------------------- launchers
 
@@ -1700,56 +1539,6 @@ hipError_t launch_phi_merge(const Ctx &c, const NextPhi &q)
     });
 }
 
-bool fused_ok_geom(int dim, int collision, const Geom &g)
-{
-    const long long Q = 27;
-    return dim == 3 && collision == 0 && g.bcx == BC_PER && g.nx <= 256 && Q * g.np < (1ll << 31);
-}
-
-bool fused_ok(const Ctx &c) { return fused_ok_geom(c.dim, c.ph.collision, c.g); }
-
-// The fused step re-reads each cell's g (and the halo rows') after the phi
-// sum and marches its tiles plane by plane with two barriers per plane.  On
-// the 128x128x512 lattice it is slower than the two-launch forms in every
-// storage format (FP32 974 vs 725 us, FP64 1.84 vs 1.52 ms, FP16S 1.10 vs
-// 0.92 ms, FP16S_ALL 1.41 vs 1.19 ms), so it is never chosen by default.
-bool fused_preferred(int) { return false; }
-
-int fused_rows(int nx) { return FUSED_THREADS / fused_bx(nx); }
-
-// Planes per block: about 1024 blocks (measured faster than 512, which fill
-// the device once with long sequential marches), at least 8 planes so that
-// the two prologue planes stay cheap.
-static int fused_zc(const Ctx &c, int by)
-{
-    const int tiles_y = (c.g.ny + by - 1) / by;
-    int chunks = 1024 / tiles_y;
-    if (chunks < 1) chunks = 1;
-    int zc = (c.g.nz + chunks - 1) / chunks;
-    if (zc < 8) zc = 8;
-    return zc;
-}
-
-hipError_t launch_step_fused(const Ctx &c)
-{
-    const int by = fused_rows(c.g.nx);
-    const int zc = fused_zc(c, by);
-    const dim3 grid(1, (c.g.ny + by - 1) / by, (c.g.nz + zc - 1) / zc);
-    return dispatch(c, [&]<int D, class P>() {
-        if constexpr (D != 3) {
-            return hipErrorInvalidValue;
-        } else {
-            if (c.ph.cac_edf)
-                hipLaunchKernelGGL((k_fused<3, P, 2>), grid, dim3(FUSED_THREADS), 0, c.stream,
-                                   c.g, to_phys<typename P::T>(c.ph), c.p, zc);
-            else
-                hipLaunchKernelGGL((k_fused<3, P, 0>), grid, dim3(FUSED_THREADS), 0, c.stream,
-                                   c.g, to_phys<typename P::T>(c.ph), c.p, zc);
-            return hipGetLastError();
-        }
-    });
-}
-
 hipError_t launch_init(const Ctx &c, const double *phi, const double *u, const double *pr)
 {
     return dispatch(c, [&]<int D, class P>() {
@@ -1799,17 +1588,18 @@ hipError_t launch_field(const Ctx &c, int field, double *dst)
 
 int nphi_block_threads(int storage) { return nphi_threads(storage); }
 
-hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool fused,
+hipError_t launch_batch_step(int dim, int storage, int collision, bool row,
                              const BatchDom *doms, const BatchTile *tiles, const int *ntiles,
                              const long long *tbase, int step_off, dim3 block, const int *grid,
-                             hipStream_t stream)
+                             int *status, hipStream_t stream)
 {
     Ctx c{};
     c.dim = dim;
     c.storage = storage;
 
     auto go = [&](auto k, dim3 blk, int nblk) {
-        hipLaunchKernelGGL(k, dim3(nblk), blk, 0, stream, doms, tiles, ntiles, tbase, step_off);
+        hipLaunchKernelGGL(k, dim3(nblk), blk, 0, stream, doms, tiles, ntiles, tbase, step_off,
+                           status);
         return hipGetLastError();
     };
     // the phi-summing domains' update (plain phase-field storage only), one
@@ -1842,11 +1632,6 @@ hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool
     // collision: the operator code (bit 0 flow collision, bit 1 first-order
     // phase-field equilibrium), shared by every domain of the batch
     return dispatch(c, [&]<int D, class P>() {
-        if constexpr (D == 3) {
-            if (fused && collision == 0) return go(kb_fused<3, P, 0>, dim3(FUSED_THREADS), grid[0]);
-            if (fused && collision == 2) return go(kb_fused<3, P, 2>, dim3(FUSED_THREADS), grid[0]);
-        }
-        if (fused) return hipErrorInvalidValue;
         hipError_t e = row ? go(kb_step<D, P, 0, true, true>, block, grid[0])
                            : go(kb_step<D, P, 0, true, false>, block, grid[0]);
         if (e != hipSuccess) return e;
@@ -1868,6 +1653,13 @@ hipError_t launch_batch_step(int dim, int storage, int collision, bool row, bool
 hipError_t launch_set_i64(long long *ptr, long long v, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, stream, ptr, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int *ptr, int n, int v, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, stream, ptr, n, v);
     return hipGetLastError();
 }
 

@@ -82,9 +82,11 @@ def load_library():
     lib.mplb_reduce.argtypes = [vp, dp]
     lib.mplb_get_populations.argtypes = [vp, ctypes.c_int32, dp]
     lib.mplb_set_populations.argtypes = [vp, ctypes.c_int32, dp]
+    lib.mplb_save_bytes.argtypes = [vp]
+    lib.mplb_save_bytes.restype = ctypes.c_size_t
+    lib.mplb_save.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.mplb_load.argtypes = [vp, vp, ctypes.c_size_t]
     lib.mplb_set_block.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
-    lib.mplb_set_fused.argtypes = [vp, ctypes.c_int32]
-    lib.mplb_uses_fused.argtypes = [vp]
     lib.mplb_set_phi_partials.argtypes = [vp, ctypes.c_int32]
     lib.mplb_uses_phi_partials.argtypes = [vp]
     lib.mplb_destroy.argtypes = [vp]
@@ -97,13 +99,12 @@ def load_library():
                                       ctypes.c_int64, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     lib.mplb_batch_set_block.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.mplb_batch_set_graph_chunk.argtypes = [vp, ctypes.c_int32]
-    lib.mplb_batch_set_fused.argtypes = [vp, ctypes.c_int32]
-    lib.mplb_batch_uses_fused.argtypes = [vp]
     lib.mplb_batch_tune_block.argtypes = [vp, ctypes.c_int32, i32p, ctypes.c_int32, i32p, dp]
     lib.mplb_batch_attach.argtypes = [vp, vp, ctypes.c_int64, i32p]
     lib.mplb_batch_detach.argtypes = [vp, ctypes.c_int32]
     lib.mplb_batch_step.argtypes = [vp, ctypes.c_int64]
     lib.mplb_batch_remaining.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+    lib.mplb_batch_status.argtypes = [vp, i32p]
     lib.mplb_batch_steps_done.argtypes = [vp]
     lib.mplb_batch_steps_done.restype = ctypes.c_int64
     lib.mplb_batch_destroy.argtypes = [vp]
@@ -258,16 +259,18 @@ class Solver:
         assert a.size == self.Q * self.N
         check(self._lib.mplb_set_populations(self.h, int(which), _dptr(a)))
 
-    def set_fused(self, mode=2):
-        """0: two-kernel step; 1: one-launch step where faster (at present nowhere); 2:
-        wherever it applies."""
-        check(self._lib.mplb_set_fused(self.h, int(mode)))
+    def save(self) -> bytes:
+        """Checkpoint of the current state (mplb_save) as bytes."""
+        n = self._lib.mplb_save_bytes(self.h)
+        buf = ctypes.create_string_buffer(n)
+        check(self._lib.mplb_save(self.h, buf, n))
+        return buf.raw
 
-    def uses_fused(self):
-        r = self._lib.mplb_uses_fused(self.h)
-        if r < 0:
-            check(r)
-        return bool(r)
+    def load(self, blob: bytes):
+        """Resume from a checkpoint written by save() of a solver with equal
+        parameters (mplb_load)."""
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        check(self._lib.mplb_load(self.h, buf, len(blob)))
 
     def set_phi_partials(self, mode=1):
         """0: phi by the pull sum each step; 1: from the partial sums the
@@ -328,6 +331,7 @@ class Batch:
                                     ctypes.c_void_p(base + off), nbytes,
                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self.h = h
+        self.capacity = int(capacity)
         self.members = {}
 
     def __del__(self):
@@ -341,17 +345,6 @@ class Batch:
 
     def set_graph_chunk(self, chunk):
         check(self._lib.mplb_batch_set_graph_chunk(self.h, int(chunk)))
-
-    def set_fused(self, mode=2):
-        """0: two-kernel step; 1: one-launch step where faster (at present nowhere); 2:
-        wherever it applies."""
-        check(self._lib.mplb_batch_set_fused(self.h, int(mode)))
-
-    def uses_fused(self):
-        r = self._lib.mplb_batch_uses_fused(self.h)
-        if r < 0:
-            check(r)
-        return bool(r)
 
     def tune_block(self, steps=4, candidates=None):
         """Fastest block shape for the attached domains (advances them; tune a copy)."""
@@ -385,3 +378,11 @@ class Batch:
 
     def steps_done(self):
         return self._lib.mplb_batch_steps_done(self.h)
+
+    def status(self):
+        """{slot: OK or EUNSTABLE} for the attached slots (mplb_batch_status);
+        unstable slots are retired by the call."""
+        cap = self.capacity
+        arr = (ctypes.c_int32 * cap)()
+        check(self._lib.mplb_batch_status(self.h, arr))
+        return {k: int(arr[k]) for k in range(cap) if arr[k] != ESTATE}

@@ -11,6 +11,9 @@ others run joins at the next step boundary. A finished solve is read back
 The baseline server runs one request at a time to completion, in arrival
 order, each as a plain solver with its own launches.
 
+A solve whose state turns non-finite is retired after the quantum in which
+the batch flagged it, and reported unstable.
+
 Every device operation goes through the C ABI (``mplb``). This module only
 schedules. Latency is measured from a request's arrival to its result being
 on the host, on a clock that starts when the replay starts.
@@ -137,6 +140,19 @@ def serve_batched(specs, dim=2, storage="fp32", hbm_budget=8 << 30, capacity=64,
         # a full quantum: a solve whose window closes inside it stops at its
         # own last step (the batch skips it), and is collected after
         batch.step(quantum)
+        # a solve whose state went non-finite is retired at once (the batch
+        # flags it during the quantum and closes its window): its slot and
+        # memory go back to the queue instead of running out its steps
+        status = batch.status()
+        for sl in [sl for sl in active if status.get(sl) == mplb.EUNSTABLE]:
+            spec, s, need, t_adm, cells = active.pop(sl)
+            batch.detach(sl)
+            results.append(Result(spec["id"], spec["arrival"], t_adm, rp.now(), spec["steps"],
+                                  cells, mplb.EUNSTABLE, None))
+            used -= need
+            del s
+            if on_event:
+                on_event("unstable", spec["id"], len(active), used)
         for sl in [sl for sl in active if batch.remaining(sl) == 0]:
             spec, s, need, t_adm, cells = active.pop(sl)
             batch.detach(sl)

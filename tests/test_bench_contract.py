@@ -34,7 +34,6 @@ def test_algorithmic_bytes_follow_the_storage_sizes():
     # read and write every population once (+ phi for the two-kernel form)
     assert bench.ALG_BYTES[("fp32", 3)]["collide"] == 27 * 4 * 4 + 4
     assert bench.ALG_BYTES[("fp32", 3)]["method"] == 27 * 4 * 4 + 8
-    assert bench.ALG_BYTES[("fp32", 3)]["fused"] == 27 * 4 * 4
     assert bench.ALG_BYTES[("fp64", 3)]["collide"] == 2 * bench.ALG_BYTES[("fp32", 3)]["collide"]
     assert bench.ALG_BYTES[("fp32", 2)]["method"] == 9 * 4 * 4 + 8
 

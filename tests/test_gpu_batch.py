@@ -147,23 +147,6 @@ def test_batch_tuner_picks_a_valid_shape_and_results_stay_bitwise():
         assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
 
 
-def test_batch_fused_and_two_kernel_forms_agree_bitwise():
-    cases = small_batch_cases(count=4, seed=31)
-    steps = 9
-    out = []
-    for fused in (True, False):
-        b = mplb.Batch(3, "fp32", capacity=4, max_tiles=1 << 14)
-        b.set_graph_chunk(4)
-        b.set_fused(2 if fused else 0)
-        solvers = [solver_for(c, stream=b.stream) for c in cases]
-        for s in solvers:
-            b.attach(s, steps)
-        assert b.uses_fused() == fused
-        b.step(steps)
-        out.append([state(s) for s in solvers])
-    for (fa, ga), (fb, gb) in zip(*out):
-        assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
-
 
 def test_first_order_equilibrium_history_carries_into_a_batch():
     # stepped alone for 2 steps (history built), then 3 steps in a batch: the

@@ -1,0 +1,189 @@
+"""The HIP path against the FP64 oracle in the paper's hard regime: density
+ratio 1000 with kinematic viscosity ratio 15 and the surface tension of the
+droplet-impact cases (Sec. 3.4; We = rho_h D U0^2 / sigma, the liquid
+density), and the static drop of Sec. 3.1 at density ratio 1000 with
+sigma = 1e-3.
+
+* A splash-shaped 3-D lattice: 64 x 64 x 48, drop diameter 16 above a sheet
+  of depth 0.1 D on the bottom wall, periodic in x and y, U0 = 0.05,
+  Re = 1000, We = 8000.
+* The 2-D static drop: 96 x 96 periodic box, R = 20, W = 4.
+
+Both start from a developed state (the oracle's own state after a few steps
+from the analytic initial condition, so every population is off
+equilibrium), which the GPU receives through mplb_set_populations; the oracle
+then steps from exactly the values the GPU holds (its decoded populations).
+Bars: the phase-field set relative to its largest magnitude (FP64 1e-12,
+FP32 2e-6 per step); the flow set likewise plus the absolute round-off floor
+derived in flow_bar (in a quiescent drop f' is ~1e-5 while the collision
+works on unit-mass populations and the surface-tension force amplifies one
+rounding of phi); a few FP32 steps 10 x those; the FP16 formats in their
+stored representation (one FP16 ulp of the stored number plus an FP32 term).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2101_06769_amd import inputs
+from tests.helpers import from_abi, gpu_available, rel_err, to_abi
+from tests.test_gpu_fp16 import check_q, source_cells, stored_q
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    from paper_2101_06769_amd import mplb
+
+TOL1 = {"fp64": 1e-12, "fp32": 2e-6}
+DEVELOP = 12  # oracle steps from the analytic state to the developed one
+
+
+def splash_small():
+    return inputs.splash3d(nx=64, ny=64, nz=48, D=16.0, U0=0.05, Re=1000.0, We=8000.0)
+
+
+def drop_1000():
+    return inputs.static_droplet(dim=2, n=(96, 96, 1), R=20.0, sigma=1e-3, rho_ratio=1000.0,
+                                 nu=0.1, W=4.0)
+
+
+CASES = {"splash3d": splash_small, "drop2d": drop_1000}
+_developed = {}
+
+
+def developed(name):
+    """(case, oracle params, f, g): the oracle's state DEVELOP steps after
+    the analytic initial condition (computed once per test session)."""
+    if name not in _developed:
+        case = CASES[name]()
+        po = oracle.params_from_dict(case.params)
+        f, g = oracle.init(po, case.phi, case.u, case.p)
+        f, g = oracle.step(po, f, g, DEVELOP)
+        _developed[name] = (case, po, f, g)
+    return _developed[name]
+
+
+def test_regime_is_the_papers():
+    case = splash_small()
+    p = case.params
+    assert p["rho_h"] / p["rho_l"] == pytest.approx(1000.0)
+    assert p["nu_l"] / p["nu_h"] == pytest.approx(15.0)
+    D, U0 = case.meta["D"], case.meta["U0"]
+    assert p["rho_h"] * D * U0 ** 2 / p["sigma"] == pytest.approx(8000.0)
+    d = drop_1000().params
+    assert d["rho_h"] / d["rho_l"] == pytest.approx(1000.0) and d["sigma"] == 1e-3
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_init_matches_oracle(name, storage):
+    case = CASES[name]()
+    dim = case.params["dim"]
+    po = oracle.params_from_dict(case.params)
+    f0, g0 = oracle.init(po, case.phi, case.u, case.p)
+    s = mplb.Solver(case.params, storage=storage)
+    s.init(case.phi, case.u, case.p)
+    assert rel_err(from_abi(dim, s.get_populations(0)), f0) < TOL1[storage]
+    assert rel_err(from_abi(dim, s.get_populations(1)), g0) < TOL1[storage]
+
+
+def _gpu_from(case, storage, f, g):
+    dim = case.params["dim"]
+    s = mplb.Solver(case.params, storage=storage)
+    s.init(case.phi, case.u, case.p)
+    s.set_populations(0, to_abi(dim, f))
+    s.set_populations(1, to_abi(dim, g))
+    return s, from_abi(dim, s.get_populations(0)), from_abi(dim, s.get_populations(1))
+
+
+EPS = {"fp64": 2.0 ** -52, "fp32": 2.0 ** -23}
+
+
+def flow_bar(storage, case, po, f_ref, g_ref):
+    """Absolute bar for one step of the flow set (Sec. 2.3), from the
+    arithmetic: the relative bar times the largest |f'|, plus the absolute
+    round-off the step cannot avoid when f' is tiny (a quiescent drop):
+    * the oracle's collision acts on the unit-mass set h ~ w (Eq.
+      LMNA_distribution preconditioned), so its own FP64 round-off sits at
+      ~eps64 rho_h cs^2;
+    * the GPU holds phi in its storage type; the Laplacian amplifies one
+      rounding of phi (|dphi| <= eps) by up to 12 (Sec. 2.2 stencil,
+      6 sum w |dphi_x + dphi|), the chemical potential multiplies it by kappa
+      (Sec. 2.1), the force by |grad phi|; a population carries it through
+      the source (Gamma c.F/2) and the half-force velocity (w rho cs^2 3 c.u
+      with u = F/(2 rho)): about w |dF| <= (4/9) 12 eps kappa |grad phi|.
+    Both terms are taken with a factor 2-4 of margin."""
+    p = case.params
+    kappa = 1.5 * p["sigma"] * p["W"]
+    grad, _ = oracle.gradients(po, oracle.fields(po, f_ref, g_ref)["phi"])
+    gmax = float(np.sqrt((grad ** 2).sum(axis=0)).max())
+    return (TOL1[storage] * float(np.abs(f_ref).max()) + 32 * EPS["fp64"] * p["rho_h"] / 3.0 +
+            24 * EPS[storage] * kappa * gmax)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_one_step_from_developed_state(name, storage):
+    case, po, f, g = developed(name)
+    dim = case.params["dim"]
+    s, f0, g0 = _gpu_from(case, storage, f, g)
+    s.step(1)
+    f1, g1 = oracle.step(po, f0, g0, 1)
+    df = np.abs(from_abi(dim, s.get_populations(0)) - f1).max()
+    eg = rel_err(from_abi(dim, s.get_populations(1)), g1)
+    bar = flow_bar(storage, case, po, f0, g0)
+    print("ratio 1000 %s %s one step: max|df'| %.2e (bar %.2e, max|f'| %.2e), g rel %.2e" %
+          (name, storage, df, bar, np.abs(f1).max(), eg))
+    assert df < bar and eg < TOL1[storage], (df, bar, eg)
+    # the light phase on its own: f' there is ~1000x smaller, the same bar
+    light = oracle.fields(po, f1, g1)["phi"] < 0.01
+    if light.any():
+        dl = np.abs(from_abi(dim, s.get_populations(0))[:, light] - f1[:, light]).max()
+        print("  light phase max|df'| %.2e" % dl)
+        assert dl < bar, dl
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fp32_few_steps_from_developed_state(name):
+    case, po, f, g = developed(name)
+    dim = case.params["dim"]
+    s, f0, g0 = _gpu_from(case, "fp32", f, g)
+    n = 5
+    s.step(n)
+    fn, gn = oracle.step(po, f0, g0, n)
+    df = np.abs(from_abi(dim, s.get_populations(0)) - fn).max()
+    eg = rel_err(from_abi(dim, s.get_populations(1)), gn)
+    bar = flow_bar("fp32", case, po, f0, g0)
+    want = oracle.fields(po, fn, gn)
+    got = s.fields()
+    du = np.abs(got["u"] - want["u"]).max()
+    dphi = np.abs(got["phi"] - want["phi"]).max()
+    print("ratio 1000 %s FP32 %d steps: max|df'| %.2e (bar %.2e) g rel %.2e max|dphi| %.2e "
+          "max|du| %.2e" % (name, n, df, bar, eg, dphi, du))
+    assert df < 10 * bar and eg < 10 * TOL1["fp32"], (df, bar, eg)
+    # phase mass: FP64 reduction of the FP32 state
+    red, rc = s.reduce()
+    assert rc == mplb.OK
+    m0 = oracle.fields(po, f0, g0)["phi"].sum()
+    assert abs(red[0] - m0) / m0 < 1e-6
+
+
+@pytest.mark.parametrize("storage", ["fp16s", "fp16s_all"])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fp16_one_step_in_stored_representation(name, storage):
+    case, po, f, g = developed(name)
+    dim = case.params["dim"]
+    s, f0, g0 = _gpu_from(case, storage, f, g)
+    s.step(1)
+    f1, g1 = oracle.step(po, f0, g0, 1)
+    fl = oracle.fields(po, f0, g0)  # time level n: the references the writers use
+    src = source_cells(dim, case.params["n"], case.params["bc"])
+    qo = stored_q(dim, to_abi(dim, f1), fl["p"], fl["rho"] / 3.0, src)
+    qg = stored_q(dim, s.get_populations(0), fl["p"], fl["rho"] / 3.0, src)
+    slack = 4e-6 * (np.abs(qo).max() + np.abs(fl["p"]).max() / (fl["rho"].min() / 3.0))
+    check_q(qg, qo, slack)
+    if storage == "fp16s":
+        assert rel_err(from_abi(dim, s.get_populations(1)), g1) < 2e-6
+    else:
+        qo = stored_q(dim, to_abi(dim, g1), fl["phi"], np.ones_like(fl["phi"]), src)
+        qg = stored_q(dim, s.get_populations(1), fl["phi"], np.ones_like(fl["phi"]), src)
+        check_q(qg, qo, 4e-6 * (np.abs(qo).max() + np.abs(fl["phi"]).max()))

@@ -46,7 +46,6 @@ CASES = [
 
 def run(params, storage, state, fields, steps, mode, block=None):
     s = gpu_solver(params, storage, state=state, fields=fields)
-    s.set_fused(0)  # the one-launch step (FP16 default) keeps phi on chip instead
     if block:
         s.set_block(*block)
     s.set_phi_partials(mode)
@@ -144,7 +143,6 @@ def test_selection_and_fallbacks():
         s2 = gpu_solver(params2, "fp32", fields=(phi2, u2, p2))
         assert not s2.uses_phi_partials(), (n, bc)
     s3 = gpu_solver(params, "fp16s_all", fields=(phi, u, p))
-    s3.set_fused(0)
     assert not s3.uses_phi_partials()
 
 

@@ -288,7 +288,6 @@ def test_row_and_lane_addressing_agree_bitwise(storage, dim, n, bc):
     out = []
     for blk in blocks:
         s = gpu_solver(params, storage, state=(f, g), fields=(phi, u, p))
-        s.set_fused(0)  # the block shape applies to the two-kernel step
         s.set_block(*blk)
         s.step(3)
         out.append((blk, s.get_populations(0), s.get_populations(1), s.fields()["phi"]))
@@ -300,68 +299,6 @@ def test_row_and_lane_addressing_agree_bitwise(storage, dim, n, bc):
         f3, g3 = oracle.step(po, f, g, 3)
         assert rel_err(from_abi(dim, out[0][1]), f3) < 10 * TOL1[storage]
         assert rel_err(from_abi(dim, out[0][2]), g3) < 10 * TOL1[storage]
-
-
-# The one-launch step (phi into LDS, then the update) applies to 3-D lattices
-# periodic in x with rows of at most 256 cells; it must reproduce the
-# two-kernel step bit for bit: partial tiles in y, several plane chunks in z,
-# every boundary type in y and z.
-FUSED_CONFIGS = [
-    (3, (21, 10, 9), (0, 0, 1)),     # one row tile of 64, walls in z
-    (3, (70, 6, 5), (0, 1, 2)),      # 128-wide tile, partial y tile, symmetry z
-    (3, (5, 4, 3), (0, 2, 1)),       # tiny
-    (3, (64, 9, 20), (0, 1, 1)),     # walls y and z, 8 rows per tile (partial)
-    (3, (130, 5, 17), (0, 0, 0)),    # 256-wide tile, fully periodic, three z chunks
-    (3, (128, 3, 40), (0, 0, 1)),    # five z chunks
-]
-
-
-@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16s", "fp16s_all"])
-@pytest.mark.parametrize("dim,n,bc", FUSED_CONFIGS)
-def test_fused_step_equals_two_kernel_step_bitwise(storage, dim, n, bc):
-    params, phi, u, p = random_case(dim, n, bc, seed=23)
-    po, f, g = noisy_state(params, phi, u, p, seed=29, amp=0.03)
-    out = []
-    for fused in (True, False):
-        s = gpu_solver(params, storage, state=(f, g), fields=(phi, u, p))
-        s.set_fused(2 if fused else 0)
-        s.set_phi_partials(0)  # the two-kernel step with the pull sum of phi
-        assert s.uses_fused() == fused
-        s.step(3)
-        out.append((s.get_populations(0), s.get_populations(1), s.fields()["phi"]))
-    for k in range(3):
-        assert np.array_equal(out[0][k], out[1][k]), (storage, k)
-    if storage in TOL1:
-        f3, g3 = oracle.step(po, f, g, 3)
-        assert rel_err(from_abi(dim, out[0][0]), f3) < 10 * TOL1[storage]
-        assert rel_err(from_abi(dim, out[0][1]), g3) < 10 * TOL1[storage]
-
-
-def test_fused_step_selection():
-    # default: the two-launch step in every format (the one-launch step is
-    # the slower one); mode 2 takes it wherever it applies
-    params, phi, u, p = random_case(3, (16, 4, 4), (0, 0, 1), seed=1)
-    for storage in ("fp32", "fp64", "fp16s", "fp16s_all"):
-        s = gpu_solver(params, storage, fields=(phi, u, p))
-        assert not s.uses_fused(), storage
-        s.set_fused(2)
-        assert s.uses_fused(), storage
-    params, phi, u, p = random_case(3, (300, 4, 4), (0, 0, 1), seed=1)
-    s = gpu_solver(params, "fp32", fields=(phi, u, p))
-    s.set_fused(2)
-    assert not s.uses_fused()  # rows longer than 256 cells
-    params, phi, u, p = random_case(3, (16, 4, 4), (1, 0, 0), seed=1)
-    s = gpu_solver(params, "fp32", fields=(phi, u, p))
-    s.set_fused(2)
-    assert not s.uses_fused()  # walls in x
-    params, phi, u, p = random_case(3, (16, 4, 4), (0, 1, 1), seed=1, collision=1)
-    s = gpu_solver(params, "fp32", fields=(phi, u, p))
-    s.set_fused(2)
-    assert not s.uses_fused()  # single relaxation time
-    params, phi, u, p = random_case(2, (64, 8, 1), (0, 1, 0), seed=1)
-    s = gpu_solver(params, "fp32", fields=(phi, u, p))
-    s.set_fused(2)
-    assert not s.uses_fused()  # 2-D
 
 
 # First-order phase-field equilibrium with the correction term (Sec. 2.2):
@@ -386,16 +323,3 @@ def test_first_order_phase_field_equilibrium_matches_oracle(storage, dim, n, bc)
     p2 = oracle.params_from_dict(dict(params, cac_edf=0))
     _, g3b = oracle.step(p2, f, g, 3)
     assert rel_err(g3b, g3) > 100 * TOL1[storage]
-
-
-@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
-def test_first_order_equilibrium_fused_and_two_kernel_agree(storage):
-    params, phi, u, p = random_case(3, (70, 6, 5), (0, 1, 2), seed=43)
-    params["cac_edf"] = 1
-    out = []
-    for mode in (2, 0):
-        s = gpu_solver(params, storage, fields=(phi, u, p))
-        s.set_fused(mode)
-        s.step(4)
-        out.append((s.get_populations(0), s.get_populations(1)))
-    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
