@@ -270,10 +270,12 @@ void mplb_destroy(mplb_solver *s);
 
 /* ---------------------------------------------------------------------------
  * Batches (design, not in the paper): many independent solvers of one
- * dimension and storage format advance together over a tile list that covers
- * every attached lattice, one block per tile: per step a phi launch and an
- * update launch, plus one launch per row length (64, 128, 192, 256, 512) for
- * the solvers whose update sums the next phi (mplb_set_phi_partials).  Each
+ * dimension and storage format advance together.  The small ones share
+ * launches over a tile list that covers every such lattice, one block per
+ * tile: per step a phi launch and an update launch, plus one launch per row
+ * length (64, 128, 192, 256, 512) for the solvers whose update sums the next
+ * phi (mplb_set_phi_partials); large ones step with their own kernels beside
+ * them (mplb_batch_set_solo_cells).  Each
  * attached solver has its own parameters, lattice size and activity window;
  * a solver's result is identical whether it is stepped alone or in a batch
  * (same per-cell arithmetic, same step form).  Steps are replayed from a
@@ -325,6 +327,18 @@ int mplb_batch_detach(mplb_batch *b, int32_t slot);
 /* Advance the batch by nsteps (asynchronous): every attached solver whose
  * window covers a step is advanced by it. */
 int mplb_batch_step(mplb_batch *b, int64_t nsteps);
+
+/* Domains of at least min_cells cells (default 2^20) fill the GPU on their
+ * own: a batch steps each with its solver's own kernels (the same ones
+ * mplb_step launches, same results), on the solvers' stream, while the
+ * smaller domains share the batched launches, replayed from the captured
+ * graph on a second stream of the batch, so that the two overlap.  0: every
+ * domain steps alone; a value above every domain's size: all share.
+ * Applies to solvers attached after the call.  mplb_batch_is_solo: 1 if the
+ * solver in `slot` steps alone, 0 if it shares the batched launches, <0 on
+ * error.  Errors: EINVAL. */
+int mplb_batch_set_solo_cells(mplb_batch *b, int64_t min_cells);
+int mplb_batch_is_solo(const mplb_batch *b, int32_t slot);
 
 /* Steps the solver in `slot` still has to take (0 = finished or retired). */
 int mplb_batch_remaining(const mplb_batch *b, int32_t slot, int64_t *remaining);

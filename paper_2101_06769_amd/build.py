@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmplb.so")
-SOURCES = ["kernels.hip", "api.cpp"]
+SOURCES = ["k_step.hip", "k_nphi.hip", "k_host.hip", "k_batch.hip", "api.cpp"]
 
 # hipcc flags: gfx950 only, C++20, no packed-FP32 instructions, and
 # multiply-add fusion only within one source expression (-ffp-contract=on):
@@ -48,17 +48,18 @@ def build(verbose: bool = False) -> str:
     """Compile every source to an object in parallel, then link the library."""
     from concurrent.futures import ThreadPoolExecutor
 
+    import tempfile
+
     inc = ["-I", os.path.join(ROOT, "include")]
     cflags = [f for f in HIPCC_FLAGS if f != "-shared"] + inc + ["-c"]
-    objs = [os.path.join(CSRC, os.path.splitext(s)[0] + ".o") for s in SOURCES]
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
-        jobs = [ex.submit(_compile, cflags + ["-x", "hip", os.path.join(CSRC, s)], o, verbose)
-                for s, o in zip(SOURCES, objs)]
-        for j in jobs:
-            j.result()
-    _compile(["--offload-arch=gfx950", "-shared", "-fPIC", "--hip-link"] + objs, LIB, verbose)
-    for o in objs:
-        os.remove(o)
+    with tempfile.TemporaryDirectory(prefix="mplb_build_") as tmp:
+        objs = [os.path.join(tmp, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        with ThreadPoolExecutor(len(SOURCES)) as ex:
+            jobs = [ex.submit(_compile, cflags + ["-x", "hip", os.path.join(CSRC, s)], o, verbose)
+                    for s, o in zip(SOURCES, objs)]
+            for j in jobs:
+                j.result()
+        _compile(["--offload-arch=gfx950", "-shared", "-fPIC", "--hip-link"] + objs, LIB, verbose)
     return LIB
 
 

@@ -54,7 +54,7 @@ struct Layout {
     int Q;
     long long N, np;
     size_t sF, sG, sT;
-    size_t F[2], G[2], phi, fp[2], fr[2], gp[2], phiu[2], npart, nedge, partials, result, total;
+    size_t F[2], G[2], phi, ref, frest[2], grest[2], phiu[2], npart, nedge, partials, result, total;
     size_t staging_bytes;
     size_t bF, bG;  // bytes of one population set of each kind (rounded to ALIGN)
 };
@@ -94,7 +94,7 @@ bool validate(const mplb_params *p, std::string &why)
 bool nphi_geom(const mplb_params *p)
 {
     auto per_or_wall = [](int b) { return b == MPLB_BC_PERIODIC || b == MPLB_BC_WALL; };
-    return p->dim == 3 && p->storage != MPLB_STORE_FP16S_ALL && p->bc[0] == MPLB_BC_PERIODIC &&
+    return p->dim == 3 && p->bc[0] == MPLB_BC_PERIODIC &&
            per_or_wall(p->bc[1]) && per_or_wall(p->bc[2]) &&
            mplb::nphi_width_ok(p->n[0], p->storage);
 }
@@ -120,20 +120,26 @@ Layout make_layout(const mplb_params *p)
     L.staging_bytes = bF + bG;
     L.bF = bF;
     L.bG = bG;
+    // phi of the current level; FP16 formats: 8-byte records (phi and the
+    // cell's packed references), the reference array the update writes, and
+    // the rest-direction values of each FP16 set in FP32, two levels
     L.phi = off;
-    off += up(L.np * L.sT, ALIGN);
-    const size_t bref = up(L.np * 4, ALIGN);
+    off += up(L.np * (f16 ? 8 : L.sT), ALIGN);
+    const size_t b4 = up(L.np * 4, ALIGN);
+    L.ref = 0;
+    if (f16) {
+        L.ref = off;
+        off += b4;
+    }
     for (int k = 0; k < 2; ++k) {
-        L.fp[k] = L.fr[k] = L.gp[k] = 0;
+        L.frest[k] = L.grest[k] = 0;
         if (f16) {
-            L.fp[k] = off;
-            off += bref;
-            L.fr[k] = off;
-            off += bref;
+            L.frest[k] = off;
+            off += b4;
         }
         if (p->storage == MPLB_STORE_FP16S_ALL) {
-            L.gp[k] = off;
-            off += bref;
+            L.grest[k] = off;
+            off += b4;
         }
     }
     // (phi u) of the current and previous step, [3][np] in the arithmetic
@@ -265,12 +271,11 @@ struct mplb_solver {
         c.p.Fout = F(1 - in);
         c.p.Gout = G(1 - in);
         c.p.phi = base + L.phi;
-        c.p.fp_in = static_cast<const float *>(at(L.fp[in]));
-        c.p.fr_in = static_cast<const float *>(at(L.fr[in]));
-        c.p.gp_in = static_cast<const float *>(at(L.gp[in]));
-        c.p.fp_out = static_cast<float *>(at(L.fp[1 - in]));
-        c.p.fr_out = static_cast<float *>(at(L.fr[1 - in]));
-        c.p.gp_out = static_cast<float *>(at(L.gp[1 - in]));
+        c.p.ref = static_cast<unsigned *>(at(L.ref));
+        c.p.frest_in = static_cast<const float *>(at(L.frest[in]));
+        c.p.grest_in = static_cast<const float *>(at(L.grest[in]));
+        c.p.frest_out = static_cast<float *>(at(L.frest[1 - in]));
+        c.p.grest_out = static_cast<float *>(at(L.grest[1 - in]));
         c.p.phiu_in = at(L.phiu[in]);
         c.p.phiu_out = at(L.phiu[1 - in]);
         c.p.have_prev = hist ? 1 : 0;
@@ -284,10 +289,10 @@ struct mplb_solver {
         const int k = cur;
         r.push_back({L.F[k], L.bF});
         r.push_back({L.G[k], L.bG});
-        const size_t ref = up(L.np * 4, ALIGN);
-        if (L.fp[k]) r.push_back({L.fp[k], ref});
-        if (L.fr[k]) r.push_back({L.fr[k], ref});
-        if (L.gp[k]) r.push_back({L.gp[k], ref});
+        const size_t b4 = up(L.np * 4, ALIGN);
+        if (L.ref) r.push_back({L.ref, b4});
+        if (L.frest[k]) r.push_back({L.frest[k], b4});
+        if (L.grest[k]) r.push_back({L.grest[k], b4});
         if (L.phiu[k]) r.push_back({L.phiu[k], size_t(3) * L.np * L.sT});
         if (nphi_valid) {
             r.push_back({L.npart, size_t(3) * L.np * L.sT});
@@ -491,7 +496,7 @@ int mplb_init(mplb_solver *s, const double *phi, const double *u, const double *
     else
         HIPCHK(hipMemsetAsync(dp, 0, nb, s->stream));
     const mplb::Ctx c = s->ctx_write(0);
-    if (c.p.fp_out || c.p.gp_out) HIPCHK(mplb::launch_set_refs(c, dphi, dp));
+    if (c.p.ref) HIPCHK(mplb::launch_set_refs(c, dphi, dp));
     HIPCHK(mplb::launch_init(c, dphi, du, dp));
     HIPCHK(hipStreamSynchronize(s->stream));
     s->cur = 0;
@@ -775,6 +780,17 @@ struct mplb_batch {
     long long t;  // batch steps taken
     hipGraphExec_t exec;
     bool have_graph;
+    // Domains of at least solo_min cells fill the GPU on their own: they
+    // step with their solver's own kernels (kernel arguments, no table
+    // reads) on the solvers' stream, while the others share the batched
+    // launches on `side`, so that the two overlap.  The streams meet at the
+    // start and the end of every mplb_batch_step.
+    long long solo_min;
+    std::vector<char> solo;         // per slot
+    std::vector<long long> start;   // per slot: the batch step it was attached at
+    int nshared;                    // attached slots in the batched launches
+    hipStream_t side;
+    hipEvent_t ev_main, ev_side;
 };
 
 namespace {
@@ -809,9 +825,11 @@ int upload_tables(mplb_batch *b)
     b->tiles.clear();
     // domains whose update sums the next phi, as their solver's own step
     // would
+    b->nshared = 0;
     for (int i = 0; i < b->capacity; ++i) {
         mplb_solver *s = b->slot[i];
-        if (!s) continue;
+        if (!s || b->solo[i]) continue;
+        ++b->nshared;
         mplb::BatchDom &d = b->doms[i];
         const mplb::Ctx c = s->ctx(s->cur);
         const int by = (b->dim == 3 && s->use_nphi(c)) ? s->next_phi().by : 0;
@@ -838,7 +856,7 @@ int upload_tables(mplb_batch *b)
         const size_t before = b->tiles.size();
         for (int i = 0; i < b->capacity; ++i) {
             const mplb_solver *s = b->slot[i];
-            if (!s) continue;
+            if (!s || b->solo[i]) continue;
             const int nx = s->prm.n[0], ny = s->prm.n[1], nz = s->prm.n[2];
             const int nby = b->doms[i].nphi_by;
             if (pass >= 2) {
@@ -956,6 +974,21 @@ int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t ma
     b->d_status = reinterpret_cast<int *>(base + os);
     b->slot.assign(capacity, nullptr);
     b->doms.assign(capacity, mplb::BatchDom{});
+    b->solo.assign(capacity, 0);
+    b->start.assign(capacity, 0);
+    b->solo_min = 1ll << 20;
+    b->nshared = 0;
+    // a second stream at the default priority for the batched launches
+    if (hipStreamCreate(&b->side) != hipSuccess) {
+        delete b;
+        return fail(MPLB_EDEVICE, "hipStreamCreate failed");
+    }
+    if (hipEventCreateWithFlags(&b->ev_main, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_side, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(b->side);
+        delete b;
+        return fail(MPLB_EDEVICE, "hipEventCreate failed");
+    }
     b->ntiles_host = b->ntiles_phi_host = b->ntiles_nphi_host = 0;
     // one bucket: an empty batch launches blocks that find no tile
     b->grid[0] = b->grid[1] = 4096;
@@ -971,6 +1004,9 @@ int mplb_batch_create(int32_t dim, int32_t storage, int32_t capacity, int64_t ma
     if (rc == MPLB_OK && hipStreamSynchronize(b->stream) != hipSuccess)
         rc = fail(MPLB_EDEVICE, "hipStreamSynchronize failed");
     if (rc != MPLB_OK) {
+        (void)hipEventDestroy(b->ev_main);
+        (void)hipEventDestroy(b->ev_side);
+        (void)hipStreamDestroy(b->side);
         delete b;
         return rc;
     }
@@ -1032,14 +1068,14 @@ int mplb_batch_attach(mplb_batch *b, mplb_solver *s, int64_t nsteps, int32_t *sl
     for (int j = 0; j < 2; ++j) {
         d.F[j] = s->F(j);
         d.G[j] = s->G(j);
-        d.fp[j] = static_cast<float *>(s->at(s->L.fp[j]));
-        d.fr[j] = static_cast<float *>(s->at(s->L.fr[j]));
-        d.gp[j] = static_cast<float *>(s->at(s->L.gp[j]));
+        d.frest[j] = static_cast<float *>(s->at(s->L.frest[j]));
+        d.grest[j] = static_cast<float *>(s->at(s->L.grest[j]));
         d.phiu[j] = s->at(s->L.phiu[j]);
     }
     // the domain's first batch step is b->t: history from there if it has one
     d.hist_from = s->hist ? b->t : b->t + 1;
     d.phi = s->base + s->L.phi;
+    d.ref = static_cast<unsigned *>(s->at(s->L.ref));
     // the phi-summing update: upload_tables sets nphi_by and the pointers; a
     // solver whose last update left partial sums merges them at its first
     // batch step, as its own next step would
@@ -1050,12 +1086,15 @@ int mplb_batch_attach(mplb_batch *b, mplb_solver *s, int64_t nsteps, int32_t *sl
     d.last = b->t + nsteps;
     b->slot[k] = s;
     b->doms[k] = d;
+    b->solo[k] = s->L.N >= b->solo_min ? 1 : 0;
+    b->start[k] = b->t;
     s->attached = true;
     HIPCHK(mplb::launch_fill_i32(b->d_status + k, 1, 0, b->stream));
     const int rc = upload_tables(b);
     if (rc != MPLB_OK) {
         b->slot[k] = nullptr;
         b->doms[k] = mplb::BatchDom{};
+        b->solo[k] = 0;
         s->attached = false;
         (void)upload_tables(b);
         return rc;
@@ -1071,6 +1110,7 @@ int mplb_batch_detach(mplb_batch *b, int32_t slot)
     b->slot[slot]->attached = false;
     b->slot[slot] = nullptr;
     b->doms[slot] = mplb::BatchDom{};
+    b->solo[slot] = 0;
     return upload_tables(b);
 }
 
@@ -1112,22 +1152,26 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
 {
     if (!b) return fail(MPLB_EINVAL, "batch is NULL");
     if (nsteps < 0) return fail(MPLB_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return MPLB_OK;
     const long long t0 = b->t;
+    // the batched launches follow the work queued on the solvers' stream
+    HIPCHK(hipEventRecord(b->ev_main, b->stream));
+    HIPCHK(hipStreamWaitEvent(b->side, b->ev_main, 0));
     long long done = 0;
-    while (done < nsteps) {
+    while (b->nshared > 0 && done < nsteps) {
         const long long left = nsteps - done;
-        HIPCHK(mplb::launch_set_i64(b->d_tbase, b->t, b->stream));
+        HIPCHK(mplb::launch_set_i64(b->d_tbase, b->t, b->side));
         if (b->chunk > 0 && left >= b->chunk) {
             if (!b->have_graph) {
                 hipGraph_t graph = nullptr;
-                HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+                HIPCHK(hipStreamBeginCapture(b->side, hipStreamCaptureModeThreadLocal));
                 hipError_t e = hipSuccess;
                 for (int k = 0; k < b->chunk && e == hipSuccess; ++k)
                     e = mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row,
                                                 b->d_doms, b->d_tiles, b->d_ntiles, b->d_tbase, k,
-                                                b->block, b->grid, b->d_status, b->stream);
+                                                b->block, b->grid, b->d_status, b->side);
                 // always end the capture, so that a failure leaves the stream usable
-                const hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+                const hipError_t e2 = hipStreamEndCapture(b->side, &graph);
                 if (e != hipSuccess || e2 != hipSuccess) {
                     if (graph) (void)hipGraphDestroy(graph);
                     return fail(MPLB_EDEVICE, std::string("graph capture: ") +
@@ -1139,22 +1183,44 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
                     return fail(MPLB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
                 b->have_graph = true;
             }
-            HIPCHK(hipGraphLaunch(b->exec, b->stream));
+            HIPCHK(hipGraphLaunch(b->exec, b->side));
             b->t += b->chunk;
             done += b->chunk;
         } else {
             HIPCHK(mplb::launch_batch_step(b->dim, b->storage, b->collision, b->row, b->d_doms,
                                            b->d_tiles, b->d_ntiles, b->d_tbase, 0, b->block,
-                                           b->grid, b->d_status, b->stream));
+                                           b->grid, b->d_status, b->side));
             b->t += 1;
             done += 1;
         }
     }
-    // host bookkeeping: each attached solver advanced by the overlap of its
-    // window with [t0, t); windows open at or before t0
+    b->t = t0 + nsteps;
+    // domains that step with their own kernels, on the solvers' stream while
+    // the batched launches run on the side stream; their phi is checked for
+    // non-finite values every chunk of steps and at the end
+    const int check = b->chunk > 0 ? b->chunk : 16;
     for (int i = 0; i < b->capacity; ++i) {
         mplb_solver *s = b->slot[i];
-        if (!s) continue;
+        if (!s || !b->solo[i]) continue;
+        const long long lo = t0 > b->start[i] ? t0 : b->start[i];
+        const long long hi = b->t < b->doms[i].last ? b->t : b->doms[i].last;
+        for (long long k = lo; k < hi; ++k) {
+            const mplb::Ctx c = s->ctx(s->cur);
+            HIPCHK(s->launch_phi_stage(c));
+            if ((k - lo) % check == 0) HIPCHK(mplb::launch_flag_nonfinite(c, b->d_status + i));
+            HIPCHK(s->launch_update_stage(c));
+            s->cur ^= 1;
+            s->steps++;
+            s->hist = true;
+        }
+    }
+    HIPCHK(hipEventRecord(b->ev_side, b->side));
+    HIPCHK(hipStreamWaitEvent(b->stream, b->ev_side, 0));
+    // host bookkeeping of the shared domains: each advanced by the overlap of
+    // its window with [t0, t); windows open at or before t0
+    for (int i = 0; i < b->capacity; ++i) {
+        mplb_solver *s = b->slot[i];
+        if (!s || b->solo[i]) continue;
         const long long lo = t0;
         const long long hi = b->t < b->doms[i].last ? b->t : b->doms[i].last;
         const long long adv = hi > lo ? hi - lo : 0;
@@ -1167,6 +1233,21 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
         }
     }
     return MPLB_OK;
+}
+
+int mplb_batch_set_solo_cells(mplb_batch *b, int64_t min_cells)
+{
+    if (!b) return fail(MPLB_EINVAL, "batch is NULL");
+    if (min_cells < 0) return fail(MPLB_EINVAL, "min_cells must be >= 0");
+    b->solo_min = min_cells;
+    return MPLB_OK;
+}
+
+int mplb_batch_is_solo(const mplb_batch *b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->capacity || !b->slot[slot])
+        return fail(MPLB_EINVAL, "no solver in that slot");
+    return b->solo[slot] ? 1 : 0;
 }
 
 int mplb_batch_tune_block(mplb_batch *b, int32_t steps, const int32_t *candidates, int32_t ncand,
@@ -1235,7 +1316,11 @@ void mplb_batch_destroy(mplb_batch *b)
     if (!b) return;
     for (auto *s : b->slot)
         if (s) s->attached = false;
+    (void)hipStreamSynchronize(b->side);
     drop_graph(b);
+    (void)hipEventDestroy(b->ev_main);
+    (void)hipEventDestroy(b->ev_side);
+    (void)hipStreamDestroy(b->side);
     delete b;
 }
 

@@ -34,12 +34,16 @@ struct Ptrs {
     void *Fout;
     const void *Gin;
     void *Gout;
-    void *phi;            // order parameter of the current time level
-    // FP16-shifted storage: per-cell shift and scale of the encoded values
-    const float *fp_in, *fr_in;   // f': pressure shift, rho cs^2 scale
-    float *fp_out, *fr_out;
-    const float *gp_in;           // g: phi shift
-    float *gp_out;
+    // order parameter of the current time level: [np] in the arithmetic
+    // type; FP16 formats: [np] 8-byte records (phi, packed references of the
+    // values the cell wrote a step earlier), see device.hpp "FP16 storage"
+    void *phi;
+    // FP16 formats: the packed references the update writes for the values
+    // it stores ([np]), and the rest-direction values of the FP16 sets in
+    // FP32 ([np] each, null for a set in plain storage)
+    unsigned *ref;
+    const float *frest_in, *grest_in;
+    float *frest_out, *grest_out;
     // first-order phase-field equilibrium: (phi u) per cell, [3][np], of the
     // previous step (valid when have_prev) and of this step
     const void *phiu_in;
@@ -70,7 +74,7 @@ struct NextPhi {
 };
 // The update kernel that also sums the next order parameter from the values
 // it stores, tile by tile (3-D, x periodic, nx as nphi_width_ok, y and z
-// periodic or walls, plain phase-field storage); nphi_ok tells whether it
+// periodic or walls); nphi_ok tells whether it
 // applies.  Its tiles are whole rows by nphi_rows rows, whatever
 // the block shape of the other kernels.
 bool nphi_ok(const Ctx &c);
@@ -93,8 +97,8 @@ hipError_t launch_init(const Ctx &c, const double *phi, const double *u, const d
 hipError_t launch_get_pop(const Ctx &c, int which, int a0, int a1, double *dst);
 // The inverse: src[(a-a0)][N] into the Fout/Gout buffers in pull layout.
 hipError_t launch_set_pop(const Ctx &c, int which, int a0, int a1, const double *src);
-// Per-cell shift/scale of FP16-shifted formats (the *_out arrays) from FP64
-// order-parameter and pressure fields.
+// References of the FP16 formats (the ref array) for an initial state, from
+// FP64 order-parameter and pressure fields.
 hipError_t launch_set_refs(const Ctx &c, const double *phi, const double *pr);
 // One macroscopic field of the state held in Fin/Gin (phi must be current).
 hipError_t launch_field(const Ctx &c, int field, double *dst);
@@ -108,7 +112,8 @@ struct BatchDom {
     Geom g;
     PhysD ph;
     void *F[2], *G[2], *phi;
-    float *fp[2], *fr[2], *gp[2];
+    unsigned *ref;
+    float *frest[2], *grest[2];
     void *phiu[2];
     long long first, last;  // active for batch steps first <= t < last
     long long hist_from;    // (phi u) of the previous step valid for t >= hist_from
@@ -150,9 +155,12 @@ hipError_t launch_batch_step(int dim, int storage, int collision, bool row,
                              const BatchDom *doms, const BatchTile *tiles, const int *ntiles,
                              const long long *tbase, int step_off, dim3 block, const int *grid,
                              int *status, hipStream_t stream);
-// Threads per block of the phi-summing update for a storage format.
-int nphi_block_threads(int storage);
+// Threads per block of the phi-summing update for a storage format and row length.
+int nphi_block_threads(int storage, int nx);
 hipError_t launch_set_i64(long long *ptr, long long v, hipStream_t stream);
+// *flag |= 1 if the order parameter of the context's current level (phi
+// array, as the phi stage left it) holds a non-finite value.
+hipError_t launch_flag_nonfinite(const Ctx &c, int *flag);
 // ptr[0 .. n) = v by a kernel (no memset node when captured into a graph).
 hipError_t launch_fill_i32(int *ptr, int n, int v, hipStream_t stream);
 

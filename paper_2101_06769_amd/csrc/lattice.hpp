@@ -60,10 +60,11 @@ __device__ __forceinline__ int stencil_coord(int s, int n, int bc)
 // pull streaming: the value left the source cell x - c_a in direction a; a
 // source beyond a wall means the bounced-back f*_{opp(a)}(x); a source beyond
 // a symmetry plane is the same-side cell with that velocity component
-// reversed.  Returns the direction plane in *dir and the cell in *cell.
+// reversed.  Returns the direction plane in *dir and the cell in *cell, and
+// in *bounced (if given) whether the value bounced back from a wall.
 template <int D>
 __device__ __forceinline__ void pull_src(const Geom &g, int x, int y, int z, int a, int *dir,
-                                         int *cell)
+                                         int *cell, bool *bounced = nullptr)
 {
     const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
     int sx = x - cx, sy = y - cy, sz = z - cz;
@@ -91,6 +92,7 @@ __device__ __forceinline__ void pull_src(const Geom &g, int x, int y, int z, int
         *dir = b;
         *cell = cell_of(g, sx, sy, sz);
     }
+    if (bounced) *bounced = bb;
 }
 
 // Neighbourhood of the cell a thread works on, general form: every lane

@@ -105,6 +105,8 @@ def load_library():
     lib.mplb_batch_step.argtypes = [vp, ctypes.c_int64]
     lib.mplb_batch_remaining.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
     lib.mplb_batch_status.argtypes = [vp, i32p]
+    lib.mplb_batch_set_solo_cells.argtypes = [vp, ctypes.c_int64]
+    lib.mplb_batch_is_solo.argtypes = [vp, ctypes.c_int32]
     lib.mplb_batch_steps_done.argtypes = [vp]
     lib.mplb_batch_steps_done.restype = ctypes.c_int64
     lib.mplb_batch_destroy.argtypes = [vp]
@@ -378,6 +380,17 @@ class Batch:
 
     def steps_done(self):
         return self._lib.mplb_batch_steps_done(self.h)
+
+    def set_solo_cells(self, min_cells):
+        """Domains of at least min_cells cells attached from now on step with
+        their own kernels beside the shared batched launches."""
+        check(self._lib.mplb_batch_set_solo_cells(self.h, int(min_cells)))
+
+    def is_solo(self, slot):
+        r = self._lib.mplb_batch_is_solo(self.h, int(slot))
+        if r < 0:
+            check(r)
+        return bool(r)
 
     def status(self):
         """{slot: OK or EUNSTABLE} for the attached slots (mplb_batch_status);

@@ -169,3 +169,50 @@ def test_first_order_equilibrium_history_carries_into_a_batch():
     for s, (fa, ga) in zip(solvers, ref):
         fb, gb = state(s)
         assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
+@pytest.mark.parametrize("solo_cells", [0, 5000])
+def test_domains_stepping_alone_in_a_batch_equal_alone_bitwise(solo_cells):
+    # with a low threshold some (or all) domains step with their own kernels
+    # beside the shared batched launches; bits and step counts as alone,
+    # windows opening mid-batch included
+    cases = small_batch_cases(count=5, seed=13)
+    plan = [(0, 9), (2, 5), (0, 12), (5, 4), (1, 7)]
+    alone = []
+    for c, (_, n) in zip(cases, plan):
+        s = solver_for(c)
+        s.step(n)
+        alone.append(state(s))
+    b = mplb.Batch(3, "fp32", capacity=8, max_tiles=1 << 14)
+    b.set_graph_chunk(4)
+    b.set_solo_cells(solo_cells)
+    solvers = [solver_for(c, stream=b.stream) for c in cases]
+    slots = {}
+    for t in range(14):
+        for i, (at, n) in enumerate(plan):
+            if t == at:
+                slots[i] = b.attach(solvers[i], n)
+        b.step(1 if t % 3 else 2)
+    assert [b.is_solo(slots[i]) for i in range(len(cases))] == [c.ncells >= solo_cells
+                                                                for c in cases]
+    for i, s in enumerate(solvers):
+        assert b.remaining(slots[i]) == 0
+        assert s.steps_done() == plan[i][1]
+        fb, gb = state(s)
+        assert np.array_equal(alone[i][0], fb) and np.array_equal(alone[i][1], gb), i
+
+
+def test_nonfinite_domain_stepping_alone_is_flagged():
+    cases = small_batch_cases(count=3, seed=17)
+    phi = cases[0].phi.copy()
+    phi.reshape(-1)[7] = np.nan
+    b = mplb.Batch(3, "fp32", capacity=4, max_tiles=1 << 14)
+    b.set_solo_cells(0)
+    s_bad = mplb.Solver(cases[0].params, storage="fp32", stream=b.stream)
+    s_bad.init(phi, cases[0].u, cases[0].p)
+    s_ok = solver_for(cases[1], stream=b.stream)
+    sb, so = b.attach(s_bad, 20), b.attach(s_ok, 20)
+    b.step(3)
+    st = b.status()
+    assert st[sb] == mplb.EUNSTABLE and st[so] == mplb.OK
+    assert b.remaining(sb) == 0  # retired

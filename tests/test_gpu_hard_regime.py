@@ -26,7 +26,7 @@ import pytest
 import oracle
 from paper_2101_06769_amd import inputs
 from tests.helpers import from_abi, gpu_available, rel_err, to_abi
-from tests.test_gpu_fp16 import check_q, source_cells, stored_q
+from tests.test_gpu_fp16 import check_fp16_step
 
 pytestmark = pytest.mark.gpu
 
@@ -176,14 +176,5 @@ def test_fp16_one_step_in_stored_representation(name, storage):
     s.step(1)
     f1, g1 = oracle.step(po, f0, g0, 1)
     fl = oracle.fields(po, f0, g0)  # time level n: the references the writers use
-    src = source_cells(dim, case.params["n"], case.params["bc"])
-    qo = stored_q(dim, to_abi(dim, f1), fl["p"], fl["rho"] / 3.0, src)
-    qg = stored_q(dim, s.get_populations(0), fl["p"], fl["rho"] / 3.0, src)
-    slack = 4e-6 * (np.abs(qo).max() + np.abs(fl["p"]).max() / (fl["rho"].min() / 3.0))
-    check_q(qg, qo, slack)
-    if storage == "fp16s":
-        assert rel_err(from_abi(dim, s.get_populations(1)), g1) < 2e-6
-    else:
-        qo = stored_q(dim, to_abi(dim, g1), fl["phi"], np.ones_like(fl["phi"]), src)
-        qg = stored_q(dim, s.get_populations(1), fl["phi"], np.ones_like(fl["phi"]), src)
-        check_q(qg, qo, 4e-6 * (np.abs(qo).max() + np.abs(fl["phi"]).max()))
+    check_fp16_step(dim, case.params, s.get_populations(0), s.get_populations(1), f1, g1, fl,
+                    storage)

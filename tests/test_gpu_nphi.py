@@ -70,14 +70,14 @@ def test_partial_sums_match_oracle_fp64(n, bc):
 
 # FP16S: a round-off difference in phi can move a stored FP16 f' code by one
 # step (2^-11 of the encoded deviation), so its bar is that quantum
-@pytest.mark.parametrize("storage,tol", [("fp32", 2e-5), ("fp16s", 1e-3)])
+@pytest.mark.parametrize("storage,tol", [("fp32", 2e-5), ("fp16s", 1e-3), ("fp16s_all", 1e-3)])
 @pytest.mark.parametrize("n,bc", [CASES[0], CASES[2], CASES[3], CASES[7], CASES[8],
                                   ((512, 3, 4), (0, 1, 1))])
 def test_partial_sums_match_pull_sum(storage, tol, n, bc):
     params, phi, u, p = random_case(3, n, bc, seed=sum(n) + 2)
     out = []
-    # rows of 512 cells: one row per 512-thread tile, FP32 only
-    summing = n[0] <= 256 or storage == "fp32"
+    # rows of 512 cells: one row per 512-thread tile, FP32 arithmetic only
+    summing = n[0] <= 256 or storage != "fp64"
     for mode in (1, 0):
         s = run(params, storage, None, (phi, u, p), 6, mode)
         assert s.uses_phi_partials() == (bool(mode) and summing)
@@ -143,7 +143,7 @@ def test_selection_and_fallbacks():
         s2 = gpu_solver(params2, "fp32", fields=(phi2, u2, p2))
         assert not s2.uses_phi_partials(), (n, bc)
     s3 = gpu_solver(params, "fp16s_all", fields=(phi, u, p))
-    assert not s3.uses_phi_partials()
+    assert s3.uses_phi_partials()  # FP16 phase-field values: sums of what the readers decode
 
 
 def test_batch_run_then_solo_steps():
@@ -214,8 +214,7 @@ def test_batch_with_phi_summing_domains_equals_alone_bitwise(storage, chunk):
     b = mplb.Batch(3, storage, capacity=8, max_tiles=1 << 16)
     b.set_graph_chunk(chunk)
     solvers = [batch_solver(c, storage, b.stream) for c in cases]
-    summing = storage != "fp16s_all"  # FP16 phase-field storage: the phi pass
-    want = [summing, summing, False, summing, summing] + ([True] if wide else [])
+    want = [True, True, False, True, True] + ([True] if wide else [])
     assert [s.uses_phi_partials() for s in solvers] == want
     for s in solvers:
         b.attach(s, steps)
