@@ -194,6 +194,19 @@ int mplb_read(mplb_solver *s, int32_t field, double *host_out);
  * reductions are this library's design, not in the paper. */
 int mplb_reduce(mplb_solver *s, double out[5]);
 
+/* mplb_reduce for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same reductions, same results, with the partial sums and the result in a
+ * static device array of the library instead of the solver's arena, so the
+ * call makes no allocation of any kind.  The array holds the partials of up
+ * to 1024 reduction blocks (every lattice fits: the reduction uses at most
+ * 1024 blocks; a larger need returns EINVAL with the sizes in the message)
+ * and is looked up once per device: call with the solver's device current.
+ * Every call on one device shares that array, so calls that overlap on one
+ * device (other threads, other streams) race; serialise them.  Synchronises
+ * the stream.  Errors: EINVAL, ESTATE, EDEVICE; EUNSTABLE as mplb_reduce. */
+int mplb_reduce_noalloc(mplb_solver *s, double out[5]);
+
 /* Pre-collision populations of the state at time n (which: 0 = f', 1 = g),
  * host_out[Q][N] in the population order above, decoded to double.
  * Synchronises the stream. */

@@ -609,6 +609,26 @@ int mplb_reduce(mplb_solver *s, double out[5])
     return MPLB_OK;
 }
 
+int mplb_reduce_noalloc(mplb_solver *s, double out[5])
+{
+    if (!s || !out) return fail(MPLB_EINVAL, "solver and out are required");
+    if (!s->ready) return fail(MPLB_ESTATE, "mplb_init has not been called");
+    const mplb::Ctx c = s->ctx(s->cur);
+    if (mplb::reduce_blocks(c) > mplb::reduce_scratch_max_blocks())
+        return fail(MPLB_EINVAL, "the reduction needs " + std::to_string(mplb::reduce_blocks(c)) +
+                                     " partial blocks, the static scratch holds " +
+                                     std::to_string(mplb::reduce_scratch_max_blocks()));
+    double *res = nullptr;
+    double host[8];
+    HIPCHK(mplb::launch_phi(c));
+    HIPCHK(mplb::launch_reduce_static(c, &res));
+    HIPCHK(hipMemcpyAsync(host, res, 6 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (int k = 0; k < 5; ++k) out[k] = host[k];
+    if (host[5] != 0.0) return fail(MPLB_EUNSTABLE, "non-finite values in the state");
+    return MPLB_OK;
+}
+
 int mplb_get_populations(mplb_solver *s, int32_t which, double *host_out)
 {
     if (!s || !host_out) return fail(MPLB_EINVAL, "solver and host_out are required");

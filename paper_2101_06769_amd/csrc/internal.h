@@ -106,6 +106,12 @@ hipError_t launch_field(const Ctx &c, int field, double *dst);
 // doubles), out[8] = {sum phi, sum rho ux, uy, uz, max|u|, nonfinite count}.
 hipError_t launch_reduce(const Ctx &c, double *partials, double *out);
 int reduce_blocks(const Ctx &c);
+// launch_reduce with the partials and the result in the library's static
+// device scratch (of the current device); *result receives the device
+// address of the 8 results.  hipErrorInvalidValue if the reduction needs
+// more partial blocks than the scratch holds (reduce_scratch_max_blocks).
+hipError_t launch_reduce_static(const Ctx &c, double **result);
+int reduce_scratch_max_blocks();
 
 // One domain of a batch, as the batched kernels read it from device memory.
 struct BatchDom {

@@ -1,5 +1,8 @@
 // Host exchange (initial state, populations in and out, fields) and the
 // deterministic FP64 reductions.
+#include <map>
+#include <mutex>
+
 #include "device.hpp"
 
 namespace mplb {
@@ -328,6 +331,52 @@ hipError_t launch_reduce(const Ctx &c, double *partials, double *out)
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, c.stream, partials, nb, out);
     return hipGetLastError();
+}
+
+
+// ---------------------------------------------------- static scratch
+// The reduction's partial sums and result in a file-scope device array, for
+// callers that cannot allocate device memory (see mplb_reduce_noalloc): room
+// for RED_BLOCKS blocks of 8 partials and the 8 results.  Each device holds
+// its own copy at its own address, looked up once per device; calls that
+// overlap on one device share it and race.
+constexpr int SCRATCH_DOUBLES = RED_BLOCKS * 8 + 8;
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+namespace {
+std::mutex scratch_mu;
+std::map<int, double *> scratch_ptr;  // device -> address of `scratch` there
+}  // namespace
+
+static hipError_t scratch_base(double **base)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    auto it = scratch_ptr.find(dev);
+    if (it != scratch_ptr.end()) {
+        *base = it->second;
+        return hipSuccess;
+    }
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = static_cast<double *>(ptr);
+    *base = static_cast<double *>(ptr);
+    return hipSuccess;
+}
+
+int reduce_scratch_max_blocks() { return RED_BLOCKS; }
+
+hipError_t launch_reduce_static(const Ctx &c, double **result)
+{
+    if (reduce_blocks(c) > RED_BLOCKS) return hipErrorInvalidValue;
+    double *base = nullptr;
+    const hipError_t e = scratch_base(&base);
+    if (e != hipSuccess) return e;
+    *result = base + RED_BLOCKS * 8;
+    return launch_reduce(c, base, *result);
 }
 
 }  // namespace mplb

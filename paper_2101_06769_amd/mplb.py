@@ -80,6 +80,7 @@ def load_library():
     lib.mplb_steps_done.restype = ctypes.c_int64
     lib.mplb_read.argtypes = [vp, ctypes.c_int32, dp]
     lib.mplb_reduce.argtypes = [vp, dp]
+    lib.mplb_reduce_noalloc.argtypes = [vp, dp]
     lib.mplb_get_populations.argtypes = [vp, ctypes.c_int32, dp]
     lib.mplb_set_populations.argtypes = [vp, ctypes.c_int32, dp]
     lib.mplb_save_bytes.argtypes = [vp]
@@ -247,6 +248,14 @@ class Solver:
         """(sums[5], status): sum phi, sum rho u (3), max |u|."""
         out = np.zeros(5)
         rc = self._lib.mplb_reduce(self.h, _dptr(out))
+        if rc not in (OK, EUNSTABLE):
+            check(rc)
+        return out, rc
+
+    def reduce_noalloc(self):
+        """As reduce(), with the library's static device scratch (no allocation)."""
+        out = np.zeros(5)
+        rc = self._lib.mplb_reduce_noalloc(self.h, _dptr(out))
         if rc not in (OK, EUNSTABLE):
             check(rc)
         return out, rc
