@@ -49,7 +49,7 @@ def case_of(name):
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
-@pytest.mark.parametrize("name", ["rti3d_reduced"])
+@pytest.mark.parametrize("name", ["rti3d_reduced", "splash3d_reduced"])
 def test_reduced_run_against_oracle(name, storage):
     ref = golden(name)
     meta = ref["meta"]
