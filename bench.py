@@ -63,22 +63,22 @@ def nphi_bytes(storage, rows):
 
 KERNEL_SOURCES = ("device.hpp", "k_step.hip", "k_nphi.hip", "k_host.hip", "k_batch.hip",
                   "lattice.hpp", "internal.h")
-TRAFFIC_PROFILES = {
-    "k_collide": os.path.join(ROOT, "profiles", "k_collide_k_phi_rti3d_128x128x512_fp32_hbm_bytes.md"),
-    "k_collide_nphi": os.path.join(ROOT, "profiles",
-                                   "k_collide_nphi_k_phi_merge_rti3d_128x128x512_fp32_hbm_bytes.md"),
-}
+PROFILE_KERNELS = {"k_collide_nphi": "k_phi_merge", "k_collide": "k_phi"}
+PROFILES_DIR = os.path.join(ROOT, "profiles")
 
 
-def profiled_traffic(storage, nz, kernel="k_collide"):
+def profiled_traffic(storage, workload, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary (each counter scaled by its reading for a plain copy of
-    known size).  None unless that summary was taken on this workload, for this
-    kernel and on kernel sources identical to the ones in the tree."""
+    WRITE_SIZE summary of this workload and storage (each counter scaled by its
+    reading for a plain copy of known size).  None unless such a summary exists
+    and was taken on kernel sources identical to the ones in the tree."""
     import hashlib
 
-    path = TRAFFIC_PROFILES.get(kernel)
-    if storage != "fp32" or nz != 512 or path is None or not os.path.exists(path):
+    if kernel not in PROFILE_KERNELS:
+        return None
+    path = os.path.join(PROFILES_DIR, "%s_%s_%s_%s_hbm_bytes.md" %
+                        (kernel, PROFILE_KERNELS[kernel], workload, storage))
+    if not os.path.exists(path):
         return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -567,11 +567,14 @@ def main():
                          "phi pass over the pulled populations every step")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="rti3d",
-                    choices=["rti3d", "batch", "serve", "splash", "rti2d_convergence", "stability",
-                             "splash2d", "edf"],
-                    help="rti3d: the 128x128x512 step (default); batch: 64 uneven domains, "
+                    choices=["rti3d", "rti2d", "batch", "serve", "splash", "rti2d_convergence",
+                             "stability", "splash2d", "edf"],
+                    help="rti3d: the 128x128x512 step (default); rti2d: one 2-D Rayleigh-Taylor "
+                         "domain of --n2d squared cells (the largest served size); batch: 64 "
+                         "uneven domains, "
                          "batched vs one per launch; serve: request replay; splash: "
                          "512x512x256 droplet impact in FP64 / FP32 / FP16")
+    ap.add_argument("--n2d", type=int, default=1024, help="rti2d: cells per side")
     ap.add_argument("--splash-steps", type=int, default=200)
     ap.add_argument("--domains", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=1000)
@@ -626,7 +629,20 @@ def main():
         ms = e0.elapsed_time(e1) / reps
         print(json.dumps({"copy_probe_bytes": n, "ms": ms, "GBs_read_plus_write": 2 * n / ms / 1e6}))
         return
-    case = inputs.rti3d(nz=args.nz)
+    if args.workload == "rti2d":
+        if args.storage not in ("fp32", "fp64"):
+            sys.exit("rti2d: FP32 or FP64 storage")
+        n2 = args.n2d
+        case = inputs.rti2d(nx=n2, ny=n2, amp=0.05 * n2)
+        label = ("2-D Rayleigh-Taylor, D2Q9 cumulant + D2Q9 Allen-Cahn, %dx%d, At 0.5, Re 256, W 4, "
+                 "%s storage" % (n2, n2, args.storage))
+        wtag = "rti2d_%dx%d" % (n2, n2)
+    else:
+        case = inputs.rti3d(nz=args.nz)
+        label = ("3-D Rayleigh-Taylor, D3Q27 cumulant + D3Q27 Allen-Cahn, 128x128x%d, At 0.5, "
+                 "Re 1000, W 5, %s storage" % (args.nz, args.storage))
+        wtag = "rti3d_128x128x%d" % args.nz
+    dim = case.params["dim"]
     N = case.ncells
     s = mplb.Solver(case.params, storage=args.storage)
     s.set_phi_partials(args.phi_partials)
@@ -637,16 +653,20 @@ def main():
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(s.stream)
-    ms_phi, ms_col = s.step_timed(args.steps)
+    s.step(args.steps)
     ev1.record(s.stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
+    # per-kernel launch durations for the roofline, from HIP events around
+    # each launch on the solver's stream, over as many further steps (kept out
+    # of the timed region above: the events between launches add gaps)
+    ms_phi, ms_col = s.step_timed(args.steps)
     ms_step = ms / args.steps
     mlups = N * args.steps / (ms / 1e3) / 1e6
 
     red, rc = s.reduce()
     m0 = float(case.phi.sum())
-    ab = ALG_BYTES[(args.storage, 3)]
+    ab = ALG_BYTES[(args.storage, dim)]
     rows = s.phi_partial_rows()
     if rows:
         kernel, phi_kernel = "k_collide_nphi", "k_phi_merge"
@@ -673,13 +693,12 @@ def main():
         "dtype": {"fp32": "f32", "fp64": "f64", "fp16s": "f16s+f32",
                   "fp16s_all": "f16s"}[args.storage],
         "data": "synthetic",
-        "config": {"workload": "3-D Rayleigh-Taylor, D3Q27 cumulant + D3Q27 Allen-Cahn, "
-                               "128x128x%d, At 0.5, Re 1000, W 5, %s storage" % (args.nz,
-                                                                                args.storage),
-                   "cells": N, "lattice": "D3Q27+D3Q27", "parallelism": "single GPU"},
+        "config": {"workload": label, "cells": N,
+                   "lattice": "D3Q27+D3Q27" if dim == 3 else "D2Q9+D2Q9",
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(args.storage, args.nz, kernel),
+                     "traffic": profiled_traffic(args.storage, wtag, kernel),
                      "kernel": kernel, "alg_bytes_per_cell": method_bytes,
                      "kernel_bytes_per_cell": kbytes,
                      "kernel_frac": round(kbytes * N / t_col / 1e9 / HBM_PEAK_GBS, 4),
@@ -692,7 +711,7 @@ def main():
         "status": "ok" if rc == mplb.OK else "unstable",
     }
     del s
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and dim == 3:
         slab = lambda nz: inputs.rti3d(nz=nz, amp=0.05 * 128)  # noqa: E731
         cpu, ref = cpu_baseline(slab, args.cpu_seconds)
         cpu["gpu_speedup"] = round(mlups / cpu["value"], 1)

@@ -17,17 +17,18 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_profiled_traffic_is_tied_to_the_kernel_sources(tmp_path, monkeypatch):
-    # the committed summary matches the tree; a changed source or another
-    # workload gives None
-    t = bench.profiled_traffic("fp32", 512, "k_collide")
+    # a committed summary that matches the tree gives its bytes per launch;
+    # another workload, or a summary of other kernel sources, gives None
+    wl = "rti3d_128x128x512"
+    t = bench.profiled_traffic("fp32", wl, "k_collide_nphi")
     assert t is None or 3.0e9 < t < 5.0e9
-    assert bench.profiled_traffic("fp16s", 512, "k_collide") is None
-    assert bench.profiled_traffic("fp32", 256, "k_collide") is None
-    fake = tmp_path / "p.md"
-    fake.write_text("x\n```json\n" + json.dumps({"kernel": "k_collide", "sources_sha256": "0" * 64,
+    assert bench.profiled_traffic("fp32", "rti3d_128x128x256", "k_collide_nphi") is None
+    assert bench.profiled_traffic("fp32", wl, "kb_step") is None
+    monkeypatch.setattr(bench, "PROFILES_DIR", str(tmp_path))
+    fake = tmp_path / ("k_collide_nphi_k_phi_merge_%s_fp32_hbm_bytes.md" % wl)
+    fake.write_text("x\n```json\n" + json.dumps({"kernel": "k_collide_nphi", "sources_sha256": "0" * 64,
                                                    "traffic_bytes_per_launch": 1}) + "\n```\n")
-    monkeypatch.setitem(bench.TRAFFIC_PROFILES, "k_collide", str(fake))
-    assert bench.profiled_traffic("fp32", 512, "k_collide") is None
+    assert bench.profiled_traffic("fp32", wl, "k_collide_nphi") is None
 
 
 def test_algorithmic_bytes_follow_the_storage_sizes():
