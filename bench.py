@@ -296,12 +296,39 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def splash_vs_oracle(storage):
+    """Per-field max errors against the FP64 oracle of the same droplet impact
+    on a reduced lattice (128 x 128 x 64, D = 16, 500 steps; the oracle's
+    fields stored in tests/golden/splash3d_reduced.npz on whole planes through
+    the sheet and the drop plus seeded random cells), with the oracle's own
+    sensitivity to one FP32 rounding per step beside them."""
+    from paper_2101_06769_amd import inputs, mplb
+
+    with np.load(os.path.join(ROOT, "tests", "golden", "splash3d_reduced.npz"),
+                 allow_pickle=False) as z:
+        ref = {k: z[k] for k in ("cells", "phi", "u", "p")}
+        meta = json.loads(str(z["meta"]))
+    case = inputs.splash3d(nx=128, ny=128, nz=64, D=16.0, U0=0.05, Re=1000.0, We=8000.0)
+    s = mplb.Solver(case.params, storage=storage)
+    s.init(case.phi, case.u, case.p)
+    s.step(meta["steps"])
+    got = s.fields()
+    cells = ref["cells"].astype(np.int64)
+    U, rho_h = meta["U"], meta["rho_h"]
+    return {"steps": meta["steps"], "cells_compared": int(cells.size),
+            "phi": float(np.abs(got["phi"].ravel()[cells] - ref["phi"]).max()),
+            "u_over_U0": float(np.abs(got["u"].reshape(3, -1)[:, cells] - ref["u"]).max() / U),
+            "p_over_rhoU0sq": float(np.abs(got["p"].ravel()[cells] - ref["p"]).max() / (rho_h * U * U)),
+            "oracle_fp32_rounding_floor": meta["floor_fp32_rounding"]}
+
+
 def bench_splash(args):
     """3-D droplet impact on a thin liquid sheet, 512 x 512 x 256 (density
     ratio 1000, viscosity ratio 15, We 8000, Re 1000, D = 64, sheet 0.1 D,
     U0 0.05): the same `splash_steps` steps in FP64, FP32 and FP16-shifted
-    storage.  Reports each format's MLUPS and its field errors against the
-    FP64 run (the FP64 GPU path is the one held to the oracle at 1e-12)."""
+    storage.  Reports each format's MLUPS, its field errors against the FP64
+    run, and its field errors against the FP64 oracle on a reduced lattice of
+    the same case (splash_vs_oracle)."""
     import torch
 
     from paper_2101_06769_amd import inputs, mplb
@@ -345,6 +372,8 @@ def bench_splash(args):
             rec["max_abs_dphi"] = float(np.abs(f["phi"] - ref["phi"]).max())
             rec["max_abs_du_over_U0"] = float(np.abs(f["u"] - ref["u"]).max() / U0)
             rec["max_abs_dp_over_rhoU0sq"] = float(np.abs(f["p"] - ref["p"]).max() / (U0 * U0))
+        if storage != "fp64_floor":
+            rec["vs_fp64_oracle_reduced"] = splash_vs_oracle(storage)
         out[storage] = rec
         del s, f
         torch.cuda.empty_cache()
@@ -530,6 +559,7 @@ def bench_serve(args):
     res_b, st = serve.serve_batched(specs, hbm_budget=int(args.hbm_budget_gb * (1 << 30)),
                                     capacity=args.capacity)
     wall_b = time.perf_counter() - t0
+    print("serve: batched replay done in %.1f s" % wall_b, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     res_f = serve.serve_fifo(specs)
     wall_f = time.perf_counter() - t0
@@ -549,6 +579,10 @@ def bench_serve(args):
                         peak_gb=round(st["peak_bytes"] / 2 ** 30, 2)),
         "fifo": dict(sf, wall_s=round(wall_f, 2)),
         "unstable_requests": sum(r.status == mplb.EUNSTABLE for r in res_b),
+        "unstable": [{k: (round(v, 6) if isinstance(v, float) else v)
+                      for k, v in specs[r.id].items() if k != "arrival"}
+                     for r in sorted(res_b, key=lambda r: r.id) if r.status == mplb.EUNSTABLE],
+        "unstable_fifo_ids": sorted(r.id for r in res_f if r.status == mplb.EUNSTABLE),
     }
     print(json.dumps(line), flush=True)
 
