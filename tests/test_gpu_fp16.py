@@ -34,18 +34,18 @@ if gpu_available():
     from paper_2101_06769_amd import mplb
 
 
-def source_cells(dim, n, bc):
-    """src[a, z, y, x] = flat index of the cell that wrote the value the
-    cell pulls in direction a (library order): x - c_a under periodic wrap,
-    the same-side cell beyond a symmetry plane, the cell itself when the link
-    leaves the domain through a wall (bounce-back)."""
+def source_at(dim, n, bc, x, y, z):
+    """src[a, ...] = flat index of the cell that wrote the value the cell at
+    (x, y, z) (arrays of one shape) pulls in direction a (library order):
+    x - c_a under periodic wrap, the same-side cell beyond a symmetry plane,
+    the cell itself when the link leaves the domain through a wall
+    (bounce-back)."""
     nx, ny, nz = n
     Q = 9 if dim == 2 else 27
-    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    out = np.empty((Q, nz, ny, nx), dtype=np.int64)
+    out = np.empty((Q,) + np.shape(x), dtype=np.int64)
     for a in range(Q):
         c = (a % 3 - 1, (a // 3) % 3 - 1, (a // 9 - 1) if dim == 3 else 0)
-        coords, wall = [], np.zeros(x.shape, bool)
+        coords, wall = [], np.zeros(np.shape(x), bool)
         for comp, xi, ni, bci in zip(c, (x, y, z), (nx, ny, nz), bc):
             s = xi - comp
             outside = (s < 0) | (s >= ni)
@@ -62,6 +62,13 @@ def source_cells(dim, n, bc):
         me = (z * ny + y) * nx + x
         out[a] = np.where(wall, me, src)
     return out
+
+
+def source_cells(dim, n, bc):
+    """source_at for every cell, shaped [Q][nz][ny][nx]."""
+    nx, ny, nz = n
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return source_at(dim, n, bc, x, y, z)
 
 
 def ulp16(v):
