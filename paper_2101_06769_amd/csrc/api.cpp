@@ -232,6 +232,9 @@ struct mplb_solver {
     dim3 g_block;
     bool g_nphi;
 
+    mplb_solver() = default;
+    mplb_solver(const mplb_solver &) = delete;
+    mplb_solver &operator=(const mplb_solver &) = delete;
     ~mplb_solver()
     {
         drop_graph();
@@ -303,10 +306,11 @@ struct mplb_solver {
     }
 
     // Device regions a step from the current state reads (see save / load).
-    std::vector<Region> state_regions() const
+    std::vector<Region> state_regions() const { return state_regions(cur, nphi_valid); }
+    // The same for a state at level k whose partial sums are valid or not.
+    std::vector<Region> state_regions(int k, bool with_partials) const
     {
         std::vector<Region> r;
-        const int k = cur;
         r.push_back({L.F[k], L.bF});
         r.push_back({L.G[k], L.bG});
         const size_t b4 = up(L.np * 4, ALIGN);
@@ -314,7 +318,7 @@ struct mplb_solver {
         if (L.frest[k]) r.push_back({L.frest[k], b4});
         if (L.grest[k]) r.push_back({L.grest[k], b4});
         if (L.phiu[k]) r.push_back({L.phiu[k], size_t(3) * L.np * L.sT});
-        if (nphi_valid) {
+        if (with_partials) {
             r.push_back({L.npart, size_t(3) * L.np * L.sT});
             const mplb::NextPhi q = next_phi();
             r.push_back({L.nedge, size_t(6) * (prm.n[1] / q.by) * prm.n[2] * prm.n[0] * L.sT});
@@ -821,11 +825,7 @@ int mplb_load(mplb_solver *s, const void *host_blob, size_t bytes)
     uint64_t sizes[SAVE_MAX_REGIONS];
     std::memcpy(sizes, in + sizeof(h) + sizeof(mplb_params), sizeof(sizes));
     // the regions the saved bookkeeping implies, on this solver's layout
-    mplb_solver probe = *s;
-    probe.cur = h.cur;
-    probe.nphi = h.nphi;
-    probe.nphi_valid = h.nphi_valid != 0;
-    const std::vector<Region> reg = probe.state_regions();
+    const std::vector<Region> reg = s->state_regions(h.cur, h.nphi_valid != 0);
     size_t total = head;
     if (reg.size() != h.nregions) return fail(MPLB_EINVAL, "saved state does not match the layout");
     for (size_t i = 0; i < reg.size(); ++i) {
