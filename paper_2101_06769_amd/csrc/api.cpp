@@ -1296,23 +1296,35 @@ int mplb_batch_step(mplb_batch *b, int64_t nsteps)
         }
     }
     b->t = t0 + nsteps;
-    // domains that step with their own kernels, on the solvers' stream while
-    // the batched launches run on the side stream; their phi is checked for
-    // non-finite values every chunk of steps and at the end
+    // domains that step with their own kernels (runs of steps as their step
+    // graphs), on the solvers' stream while the batched launches run on the
+    // side stream; their phi is checked for non-finite values before every
+    // graph run and every chunk of direct steps
     const int check = b->chunk > 0 ? b->chunk : 16;
     for (int i = 0; i < b->capacity; ++i) {
         mplb_solver *s = b->slot[i];
         if (!s || !b->solo[i]) continue;
         const long long lo = t0 > b->start[i] ? t0 : b->start[i];
         const long long hi = b->t < b->doms[i].last ? b->t : b->doms[i].last;
-        for (long long k = lo; k < hi; ++k) {
+        for (long long k = lo; k < hi;) {
             const mplb::Ctx c = s->ctx(s->cur);
+            const bool steady = s->hist && (!s->use_nphi(c) || s->nphi_valid);
+            if (steady && hi - k >= GRAPH_STEPS) {
+                // a run of steps as the solver's step graph, its phi checked first
+                HIPCHK(mplb::launch_flag_nonfinite(c, b->d_status + i));
+                const int rc = replay_steps(s);
+                if (rc != MPLB_OK) return rc;
+                s->steps += GRAPH_STEPS;
+                k += GRAPH_STEPS;
+                continue;
+            }
             HIPCHK(s->launch_phi_stage(c));
             if ((k - lo) % check == 0) HIPCHK(mplb::launch_flag_nonfinite(c, b->d_status + i));
             HIPCHK(s->launch_update_stage(c));
             s->cur ^= 1;
             s->steps++;
             s->hist = true;
+            ++k;
         }
     }
     HIPCHK(hipEventRecord(b->ev_side, b->side));
