@@ -152,6 +152,42 @@ def cpu_baseline(case_fn, min_seconds=10.0):
     return rec, (p, f, g, steps)
 
 
+def c1_timing():
+    """The C1 case, the 2-D Rayleigh-Taylor run of Sec. 3.2's shape (64 x 256,
+    At 0.5, Re 256, W 4, M 0.1, 2000 steps), in full: the FP64 oracle on the
+    host's threads and the GPU in FP64 from the same initial state, with the
+    per-field difference of their final states (U* = 0.06)."""
+    import torch
+
+    import oracle
+    from paper_2101_06769_amd import inputs, mplb
+
+    case = inputs.rti2d()
+    po = oracle.params_from_dict(case.params)
+    f, g = oracle.init(po, case.phi, case.u, case.p)
+    t0 = time.perf_counter()
+    f, g = oracle.step(po, f, g, case.steps)
+    t_cpu = time.perf_counter() - t0
+    want = oracle.fields(po, f, g)
+    s = mplb.Solver(case.params, storage="fp64")
+    s.init(case.phi, case.u, case.p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(case.steps)
+    s.sync()
+    t_gpu = time.perf_counter() - t0
+    got = s.fields()
+    U = inputs.U_STAR
+    work = case.ncells * case.steps
+    return {"workload": "2-D Rayleigh-Taylor 64x256, At 0.5, Re 256, 2000 steps, FP64",
+            "oracle_s": round(t_cpu, 2), "oracle_mlups": round(work / t_cpu / 1e6, 2),
+            "oracle_threads": oracle.num_threads(),
+            "gpu_fp64_s": round(t_gpu, 4), "gpu_fp64_mlups": round(work / t_gpu / 1e6, 1),
+            "max_abs_dphi": float(np.abs(got["phi"] - want["phi"]).max()),
+            "max_abs_du_over_U": float(np.abs(got["u"] - want["u"]).max() / U),
+            "max_abs_dp_over_rhoU2": float(np.abs(got["p"] - want["p"]).max() / (U * U))}
+
+
 def error_vs_oracle(case, storage, ref):
     """Per-field error of the GPU state against the FP64 oracle after the same
     steps from the same initial state: max |dphi|, max |du| / U*, max |dp| /
@@ -204,6 +240,35 @@ def error_vs_oracle(case, storage, ref):
 ERROR_FLOOR_MULTIPLE = 5.0
 # ulps of a field's magnitude allowed for evaluating it from the populations
 EVAL_ULPS = 64
+
+
+def batch_vs_oracle(cases, steps):
+    """Per-field errors of domains stepped in a batch (the shared launches)
+    against the FP64 oracle after `steps` steps from the same initial states
+    (U* = 0.06, the Rayleigh-Taylor velocity scale of every batch domain)."""
+    import oracle
+    from paper_2101_06769_amd import inputs, mplb
+
+    b = mplb.Batch(3, "fp32", capacity=len(cases), max_tiles=1 << 16)
+    solvers = []
+    for c in cases:
+        sv = mplb.Solver(c.params, storage="fp32", stream=b.stream)
+        sv.init(c.phi, c.u, c.p)
+        b.attach(sv, steps)
+        solvers.append(sv)
+    b.step(steps)
+    out = []
+    U = inputs.U_STAR
+    for c, sv in zip(cases, solvers):
+        po = oracle.params_from_dict(c.params)
+        f, g = oracle.init(po, c.phi, c.u, c.p)
+        f, g = oracle.step(po, f, g, steps)
+        want, got = oracle.fields(po, f, g), sv.fields()
+        out.append({"n": list(c.params["n"]), "steps": steps,
+                    "max_abs_dphi": float(np.abs(got["phi"] - want["phi"]).max()),
+                    "max_abs_du_over_U": float(np.abs(got["u"] - want["u"]).max() / U),
+                    "max_abs_dp_over_rhoU2": float(np.abs(got["p"] - want["p"]).max() / (U * U))})
+    return out
 
 
 def bench_batch(args):
@@ -293,6 +358,8 @@ def bench_batch(args):
         "speedup_vs_plain": round(t_plain / t_batch, 3),
         "batched_equals_plain_bitwise": bool(same),
     }
+    smallest = sorted(cases, key=lambda c: c.ncells)[:2]
+    line["two_smallest_vs_fp64_oracle"] = batch_vs_oracle(smallest, args.oracle_steps)
     print(json.dumps(line), flush=True)
 
 
@@ -612,6 +679,8 @@ def main():
     ap.add_argument("--splash-steps", type=int, default=200)
     ap.add_argument("--domains", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--oracle-steps", type=int, default=100,
+                    help="batch: steps of the two smallest domains checked against the oracle")
     ap.add_argument("--solo-cells", type=int, default=1 << 20,
                     help="batch: domains of at least this many cells step with their own "
                          "kernels beside the shared launches")
@@ -751,6 +820,7 @@ def main():
         cpu["gpu_speedup"] = round(mlups / cpu["value"], 1)
         line["cpu_baseline"] = cpu
         line["error_vs_fp64"] = error_vs_oracle(slab(128), args.storage, ref)
+        line["cpu_baseline"]["c1"] = c1_timing()
     print(json.dumps(line), flush=True)
 
 
