@@ -161,6 +161,10 @@ int mplb_init(mplb_solver *s, const double *phi, const double *u, const double *
  * the antidiffusion source (Sec. 2.2, Eqs. LBM_AC and
  * phase_source_post_discretization), and streaming with the boundary rules
  * of Sec. 3 (half-way bounce-back walls, symmetry planes, periodic axes).
+ * Runs of 16 steady-state steps are launched as one captured HIP graph (the
+ * same kernels and arguments, the same results; design, not in the paper):
+ * the graph is captured on a stream of the handle's own at the first such
+ * run and again when the level parity, the block or the step form changes.
  * Errors: EINVAL, ESTATE (not initialised, or attached to a batch),
  * EDEVICE. */
 int mplb_step(mplb_solver *s, int64_t nsteps);
@@ -278,7 +282,9 @@ int mplb_uses_phi_partials(const mplb_solver *s);
 int mplb_tune_block(mplb_solver *s, int32_t steps, const int32_t *candidates, int32_t ncand,
                     int32_t best[3], double *best_ms_per_step);
 
-/* Release the handle (the arena stays the caller's). */
+/* Release the handle, its step graph and its capture stream (the arena stays
+ * the caller's).  Waits for the handle's stream when a step graph exists, so
+ * that no replay is in flight when the graph goes. */
 void mplb_destroy(mplb_solver *s);
 
 /* ---------------------------------------------------------------------------

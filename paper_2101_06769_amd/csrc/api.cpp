@@ -237,6 +237,8 @@ struct mplb_solver {
     mplb_solver &operator=(const mplb_solver &) = delete;
     ~mplb_solver()
     {
+        // replays still in flight finish before their graph goes
+        if (have_g) (void)hipStreamSynchronize(stream);
         drop_graph();
         if (cap) (void)hipStreamDestroy(cap);
     }
