@@ -242,10 +242,12 @@ ERROR_FLOOR_MULTIPLE = 5.0
 EVAL_ULPS = 64
 
 
-def batch_vs_oracle(cases, steps):
-    """Per-field errors of domains stepped in a batch (the shared launches)
-    against the FP64 oracle after `steps` steps from the same initial states
-    (U* = 0.06, the Rayleigh-Taylor velocity scale of every batch domain)."""
+def batch_cpu_baseline(cases, steps):
+    """The batch workload's CPU leg: the FP64 oracle timed on the given
+    domains (the two smallest of the batch) for `steps` steps on the host's
+    threads, and the per-field errors of the same domains stepped in a batch
+    (the shared launches) against it (U* = 0.06, the Rayleigh-Taylor velocity
+    scale of every batch domain)."""
     import oracle
     from paper_2101_06769_amd import inputs, mplb
 
@@ -257,18 +259,26 @@ def batch_vs_oracle(cases, steps):
         b.attach(sv, steps)
         solvers.append(sv)
     b.step(steps)
-    out = []
+    errs, t_cpu, work = [], 0.0, 0
     U = inputs.U_STAR
     for c, sv in zip(cases, solvers):
         po = oracle.params_from_dict(c.params)
         f, g = oracle.init(po, c.phi, c.u, c.p)
+        t0 = time.perf_counter()
         f, g = oracle.step(po, f, g, steps)
+        t_cpu += time.perf_counter() - t0
+        work += c.ncells * steps
         want, got = oracle.fields(po, f, g), sv.fields()
-        out.append({"n": list(c.params["n"]), "steps": steps,
-                    "max_abs_dphi": float(np.abs(got["phi"] - want["phi"]).max()),
-                    "max_abs_du_over_U": float(np.abs(got["u"] - want["u"]).max() / U),
-                    "max_abs_dp_over_rhoU2": float(np.abs(got["p"] - want["p"]).max() / (U * U))})
-    return out
+        errs.append({"n": list(c.params["n"]), "steps": steps,
+                     "max_abs_dphi": float(np.abs(got["phi"] - want["phi"]).max()),
+                     "max_abs_du_over_U": float(np.abs(got["u"] - want["u"]).max() / U),
+                     "max_abs_dp_over_rhoU2": float(np.abs(got["p"] - want["p"]).max() / (U * U))})
+    return {"value": work / t_cpu / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d steps of the %d smallest domains (%s), FP64, %.1f s" %
+                      (steps, len(cases), ", ".join("x".join(map(str, c.params["n"])) for c in cases),
+                       t_cpu),
+            "cpu_model": cpu_model(), "batched_vs_oracle": errs}
 
 
 def bench_batch(args):
@@ -358,8 +368,9 @@ def bench_batch(args):
         "speedup_vs_plain": round(t_plain / t_batch, 3),
         "batched_equals_plain_bitwise": bool(same),
     }
-    smallest = sorted(cases, key=lambda c: c.ncells)[:2]
-    line["two_smallest_vs_fp64_oracle"] = batch_vs_oracle(smallest, args.oracle_steps)
+    if not args.no_cpu_baseline:
+        smallest = sorted(cases, key=lambda c: c.ncells)[:2]
+        line["cpu_baseline"] = batch_cpu_baseline(smallest, args.oracle_steps)
     print(json.dumps(line), flush=True)
 
 
