@@ -32,7 +32,8 @@
  *   - Ownership: the caller owns the device arena (any device allocation of
  *     at least mplb_state_bytes() bytes, e.g. a torch uint8 tensor) and all
  *     host buffers.  The library carves the arena and never allocates or
- *     frees device memory; it owns only its handle.
+ *     frees device memory; it owns only its handle and, once the handle has
+ *     stepped, its step graph and capture stream (mplb_step).
  *   - Stream: all device work is queued on the hipStream_t given at create
  *     time (NULL = the null stream).  Calls are asynchronous unless stated;
  *     calls that return host data synchronise that stream.
@@ -55,7 +56,7 @@ enum {
     MPLB_EINVAL = -1,    /* invalid argument or parameter */
     MPLB_ENOMEM = -2,    /* arena smaller than mplb_state_bytes() */
     MPLB_EDEVICE = -3,   /* HIP runtime error (message in mplb_last_error) */
-    MPLB_EUNSTABLE = -4, /* non-finite value found by mplb_reduce */
+    MPLB_EUNSTABLE = -4, /* non-finite value found by mplb_reduce or mplb_batch_status */
     MPLB_ESTATE = -5     /* call not valid in the handle's current state */
 };
 
@@ -72,9 +73,13 @@ enum {
 enum {
     MPLB_STORE_FP64 = 0,
     MPLB_STORE_FP32 = 1,
-    MPLB_STORE_FP16S = 2,    /* f' as FP16 deviations from w p_h, scaled by w rho cs^2;
-                                g FP32 */
-    MPLB_STORE_FP16S_ALL = 3 /* f' as above, g as FP16 deviations from w phi */
+    MPLB_STORE_FP16S = 2,    /* f': per moving direction the FP16 code
+                                q = (f'/w - P)/s against the writing cell's
+                                references P = fp16(p*), s = rho(fp16(phi)) cs^2,
+                                rest direction FP32; g FP32 */
+    MPLB_STORE_FP16S_ALL = 3 /* f' as above; g: the FP16 code q = g/w - F against
+                                the reading cell's F = fp16(phi), rest direction
+                                FP32 */
 };
 
 /* Flow collision operator. */
