@@ -7,7 +7,11 @@ test_oracle_sampled_reduce):
   Re 1000, W 5), ten steps in, with the update that sums the next phi: FP64,
   FP16S and FP16S_ALL (FP32 is in test_gpu_parity);
 * the largest served lattice, a 1024 x 1024 2-D Rayleigh-Taylor domain
-  (Sec. 3.2 shape), FP32 and FP64.
+  (Sec. 3.2 shape), FP32 and FP64;
+* the droplet impact on a thin sheet at its full size, 512 x 512 x 256
+  (Sec. 3.4; density ratio 1000, viscosity ratio 15, We 8000, Re 1000,
+  D = 64), in FP32 and FP16S, ten steps in (about 60 GB of host memory for
+  the decoded states).
 
 The oracle starts from the GPU's own decoded state at the sampled cells' level.
 The samples are seeded random cells plus both wall layers.  FP64 and FP32 are
@@ -95,24 +99,18 @@ def test_full_size_rti3d_fp64_one_step_at_sampled_cells():
     assert ef < 1e-12 and eg < 1e-12
 
 
-@pytest.mark.parametrize("storage", ["fp16s", "fp16s_all"])
-def test_full_size_rti3d_fp16_one_step_at_sampled_cells(storage):
-    case = full_rti3d()
+def check_fp16_sampled(case, storage, f, g, got_f, got_g, cells, label):
+    """FP16 stored representation at sampled cells: f, g the decoded state
+    (oracle order) the step started from; got_f, got_g the GPU's decoded
+    populations after it at the cells ([Q][m], library order)."""
     dim, params = 3, case.params
-    s, f, g, f1, g1 = run(case, storage, warm=10)
-    assert s.phi_partial_rows() > 0
     n, bc = params["n"], params["bc"]
-    cells = sample(n, 1500, seed=3)
     po = oracle.params_from_dict(params)
     fo_c, go_c = oracle.step_sampled(po, f, g, cells)
     fo = to_abi(dim, fo_c.T)  # [Q][m], library order
     go = to_abi(dim, go_c.T)
-    got_f = f1.reshape(27, -1)[:, cells]
-    got_g = g1.reshape(27, -1)[:, cells]
-    del f1, g1
     # the writers' references: fp16 of p* and phi of the level the step started from
     fl = oracle.fields(po, f, g)
-    del f, g
     refs = refs16(params, fl["phi"], fl["p"])
     nx, ny = n[0], n[1]
     x, y, z = cells % nx, (cells // nx) % ny, cells // (nx * ny)
@@ -131,8 +129,8 @@ def test_full_size_rti3d_fp16_one_step_at_sampled_cells(storage):
     qmax = np.abs(qo).max()
     bar = (1 - w[Q // 2, 0]) * s_me * ulp16(qmax) + 1e-5 * np.abs(fo).max()
     drest = np.abs(got_f[Q // 2] - fo[Q // 2])
-    print("3-D 128x128x512 %s flow: max code diff %.3g, rest diff %.2e (bar %.2e)" %
-          (storage, np.abs(qg - qo).max(), drest.max(), bar.max()))
+    print("%s %s flow: max code diff %.3g, rest diff %.2e (bar %.2e)" %
+          (label, storage, np.abs(qg - qo).max(), drest.max(), bar.max()))
     assert np.all(drest <= bar)
     if storage == "fp16s":
         assert rel_err(got_g, go) < 2e-6
@@ -146,3 +144,43 @@ def test_full_size_rti3d_fp16_one_step_at_sampled_cells(storage):
         print("  phase: max code diff %.3g, rest diff %.2e (bar %.2e)" %
               (np.abs(qg - qo).max(), dg.max(), barg))
         assert dg.max() <= barg
+
+
+@pytest.mark.parametrize("storage", ["fp16s", "fp16s_all"])
+def test_full_size_rti3d_fp16_one_step_at_sampled_cells(storage):
+    case = full_rti3d()
+    s, f, g, f1, g1 = run(case, storage, warm=10)
+    assert s.phi_partial_rows() > 0
+    cells = sample(case.params["n"], 1500, seed=3)
+    got_f = f1.reshape(27, -1)[:, cells]
+    got_g = g1.reshape(27, -1)[:, cells]
+    del f1, g1
+    check_fp16_sampled(case, storage, f, g, got_f, got_g, cells, "3-D 128x128x512")
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+def test_full_size_splash_one_step_at_sampled_cells(storage):
+    # the benchmark's droplet impact at full size; the populations are read
+    # back one set at a time and only the sampled columns of the stepped
+    # state are kept, to bound host memory
+    case = inputs.splash3d()
+    s = mplb.Solver(case.params, storage=storage)
+    s.init(case.phi, case.u, case.p)
+    s.step(10)
+    f = from_abi(3, s.get_populations(0))
+    g = from_abi(3, s.get_populations(1))
+    s.step(1)
+    cells = sample(case.params["n"], 1500, seed=4)
+    got_f = s.get_populations(0).reshape(27, -1)[:, cells]
+    got_g = s.get_populations(1).reshape(27, -1)[:, cells]
+    del s
+    if storage == "fp32":
+        po = oracle.params_from_dict(case.params)
+        fo, go = oracle.step_sampled(po, f, g, cells)
+        ef = rel_err(from_abi(3, got_f).T, fo)
+        eg = rel_err(from_abi(3, got_g).T, go)
+        print("3-D splash 512x512x256 fp32 one step at %d cells: f rel %.2e, g rel %.2e" %
+              (cells.size, ef, eg))
+        assert ef < 2e-6 and eg < 2e-6
+    else:
+        check_fp16_sampled(case, storage, f, g, got_f, got_g, cells, "3-D splash 512x512x256")
