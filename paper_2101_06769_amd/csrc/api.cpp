@@ -200,6 +200,8 @@ mplb::PhysD make_phys(const mplb_params *p)
     d.inv_tpb = 1.0 / tpb;
     d.src_pre = 1.0 - 0.5 / tpb;
     d.four_W = 4.0 / p->W;
+    d.scl_l = p->rho_light / 3.0;
+    d.dscl = (p->rho_heavy - p->rho_light) / 3.0;
     d.visc_interp = p->visc_interp;
     d.collision = p->collision;
     d.cac_edf = p->cac_edf;

@@ -222,6 +222,7 @@ __device__ __forceinline__ T phi_at(const NbRow &n, const T *phi, int cx, int cy
 template <typename T>
 struct Phys {
     T rho_l, drho, nu_l, dnu, rnu_l, drnu, beta, kappa, gx, gy, gz, inv_tpb, src_pre, four_W;
+    T scl_l, dscl;
     int visc_interp, collision, cac_edf;
 };
 
@@ -243,6 +244,8 @@ __host__ __device__ static Phys<T> to_phys(const PhysD &d)
     p.inv_tpb = T(d.inv_tpb);
     p.src_pre = T(d.src_pre);
     p.four_W = T(d.four_W);
+    p.scl_l = T(d.scl_l);
+    p.dscl = T(d.dscl);
     p.visc_interp = d.visc_interp;
     p.collision = d.collision;
     p.cac_edf = d.cac_edf;
@@ -286,16 +289,20 @@ __device__ __forceinline__ unsigned pack_ref(float P, float F)
     return unsigned(__half_as_ushort(__float2half(P))) |
            (unsigned(__half_as_ushort(__float2half(F))) << 16);
 }
-// Scale of the flow codes written by a cell whose reference has order parameter F.
+// Scale of the flow codes written by a cell whose reference has order
+// parameter F: rho(F) cs^2, with cs^2 folded into the two coefficients.
 __device__ __forceinline__ float flow_scale16(const Phys<float> &ph, float F)
 {
-    return (ph.rho_l + ph.drho * F) * (1.0f / 3.0f);
+    return __builtin_fmaf(ph.dscl, F, ph.scl_l);
 }
 __device__ __forceinline__ float dec_f16(float w, const Ref16 &r, float s, float q)
 {
     return w * (r.P + s * q);
 }
-__device__ __forceinline__ float dec_g16(float w, float F, float q) { return w * (F + q); }
+// w (F + q) as w q + w F: a reader decodes all its values against one F, so
+// w F is formed once per weight and each value takes one mixed-precision
+// multiply-add of its FP16 code.
+__device__ __forceinline__ float dec_g16(float w, float F, float q) { return __builtin_fmaf(w, q, w * F); }
 // Order-parameter record of the FP16 formats: phi (low word), reference.
 __device__ __forceinline__ float rec_phi(unsigned long long v) { return __uint_as_float(unsigned(v)); }
 __device__ __forceinline__ unsigned rec_ref(unsigned long long v) { return unsigned(v >> 32); }
@@ -436,13 +443,15 @@ __device__ __forceinline__ void velocity(Cell<T> &c)
 // would hold cost occupancy).
 constexpr bool CAC_PRELOAD = false;
 
-// Pairs of directions per group of the merged pass whose loads the compiler
-// may overlap (a scheduling fence after each group bounds the registers the
-// loads in flight hold); 0: no fence.
-constexpr int EVAL16_GROUP = 0;
-
+// Two schedules of the same pass.  paired: each pair's loads beside its
+// arithmetic, the compiler free to overlap them (FP16S_ALL).  hoisted: every
+// load of the pass (26 records, 26 codes) issued first, then a scheduling
+// fence (FP16S): there, left to itself, the compiler trades the loads in
+// flight for occupancy and waits on each pair in turn (update 600 -> 709 us
+// on 128 x 128 x 512), while with both sets in FP16 the fence or the hoisted
+// form costs it scalar-register spills.
 template <int D, class P, class NB>
-__device__ __forceinline__ void eval_cell16(const NB &nb, long long np, const Phys<float> &ph,
+__device__ __forceinline__ void eval_cell16_paired(const NB &nb, long long np, const Phys<float> &ph,
                                             const Ptrs &p, Cell<float> &c, unsigned *gref)
 {
     constexpr int Q = Lat<D>::Q;
@@ -485,8 +494,75 @@ __device__ __forceinline__ void eval_cell16(const NB &nb, long long np, const Ph
         if (cx && cy) Sxy += float(cx * cy) * sp;
         if (cx && cz) Sxz += float(cx * cz) * sp;
         if (cy && cz) Syz += float(cy * cz) * sp;
-        if (EVAL16_GROUP > 0 && (a - Q / 2) % (EVAL16_GROUP > 0 ? EVAL16_GROUP : 1) == 0)
-            __builtin_amdgcn_sched_barrier(0);
+    }
+    c.phi = p0;
+    c.gx = 3.0f * gx;
+    c.gy = 3.0f * gy;
+    c.gz = 3.0f * gz;
+    c.lap = 6.0f * lap;
+    c.S0 = S0; c.Sx = Sx; c.Sy = Sy; c.Sz = Sz;
+    c.Sxx = Sxx; c.Syy = Syy; c.Szz = Szz; c.Sxy = Sxy; c.Sxz = Sxz; c.Syz = Syz;
+    closure<D, float>(ph, c);
+    velocity<D, float>(c);
+
+}
+
+template <int D, class P, class NB>
+__device__ __forceinline__ void eval_cell16_hoisted(const NB &nb, long long np, const Phys<float> &ph,
+                                            const Ptrs &p, Cell<float> &c, unsigned *gref)
+{
+    constexpr int Q = Lat<D>::Q, H = Q / 2;
+    const unsigned long long *rec = static_cast<const unsigned long long *>(p.phi);
+    const unsigned long long r0 = phi_at(nb, rec, 0, 0, 0);
+    const float frest = own_at(nb, p.frest_in);
+    unsigned long long rp[H], rm[H];
+    unsigned short qa_bits[H], qb_bits[H];
+    auto load_pair = [&](int a) {
+        const int k = a - (H + 1), b = opposite<D>(a);
+        const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
+        rp[k] = phi_at(nb, rec, cx, cy, cz);     // x + c_a
+        rm[k] = phi_at(nb, rec, -cx, -cy, -cz);  // x - c_a
+        const PullLoc la = pull_loc<D>(nb, a), lb = pull_loc<D>(nb, b);
+        qa_bits[k] = load_loc(nb, static_cast<const unsigned short *>(p.Fin), (long long)la.dir * np, la);
+        qb_bits[k] = load_loc(nb, static_cast<const unsigned short *>(p.Fin), (long long)lb.dir * np, lb);
+    };
+#pragma unroll
+    for (int a = H + 1; a < Q; ++a) load_pair(a);
+    __builtin_amdgcn_sched_barrier(0);
+    const float p0 = rec_phi(r0);
+    const unsigned own_bits = rec_ref(r0);
+    c.Fown = unpack_ref(own_bits).F;
+    float gx = 0, gy = 0, gz = 0, lap = 0;
+    float S0 = frest;
+    float Sx = 0, Sy = 0, Sz = 0, Sxx = 0, Syy = 0, Szz = 0, Sxy = 0, Sxz = 0, Syz = 0;
+#pragma unroll
+    for (int a = H + 1; a < Q; ++a) {
+        const int k = a - (H + 1), b = opposite<D>(a);
+        const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
+        const float pp = rec_phi(rp[k]), pm = rec_phi(rm[k]);
+        const float w = weight<D, float>(a);
+        const float d = w * (pp - pm);
+        if (cx) gx += float(cx) * d;
+        if (cy) gy += float(cy) * d;
+        if (cz) gz += float(cz) * d;
+        lap += w * ((pp - p0) + (pm - p0));
+        if (gref) gref[k] = unsigned(half_bits(pp)) | (unsigned(half_bits(pm)) << 16);
+        const PullLoc la = pull_loc<D>(nb, a), lb = pull_loc<D>(nb, b);
+        const float qa = half_val(qa_bits[k]), qb = half_val(qb_bits[k]);
+        // the reference words selected as integers: no branch on the
+        // (wavefront-uniform in the row form) bounce-back flags
+        const Ref16 ra = unpack_ref(la.bb ? own_bits : rec_ref(rm[k]));
+        const Ref16 rb = unpack_ref(lb.bb ? own_bits : rec_ref(rp[k]));
+        const float va = dec_f16(w, ra, flow_scale16(ph, ra.F), qa);
+        const float vb = dec_f16(w, rb, flow_scale16(ph, rb.F), qb);
+        const float sp = va + vb, dm = va - vb;
+        S0 += sp;
+        if (cx) { Sx += float(cx) * dm; Sxx += sp; }
+        if (cy) { Sy += float(cy) * dm; Syy += sp; }
+        if (cz) { Sz += float(cz) * dm; Szz += sp; }
+        if (cx && cy) Sxy += float(cx * cy) * sp;
+        if (cx && cz) Sxz += float(cx * cz) * sp;
+        if (cy && cz) Syz += float(cy * cz) * sp;
     }
     c.phi = p0;
     c.gx = 3.0f * gx;
@@ -506,7 +582,10 @@ __device__ __forceinline__ void eval_cell(const NB &nb, long long np,
 {
     using T = typename P::T;
     if constexpr (P::F::shifted) {
-        eval_cell16<D, P>(nb, np, ph, p, c, gref);
+        if constexpr (P::G::shifted)
+            eval_cell16_paired<D, P>(nb, np, ph, p, c, gref);
+        else
+            eval_cell16_hoisted<D, P>(nb, np, ph, p, c, gref);
     } else {
         stencil<D, T>(nb, static_cast<const T *>(p.phi), c);
         closure<D, T>(ph, c);
@@ -566,9 +645,34 @@ __device__ __forceinline__ void rebuild(T ux, T uy, T uz, T dxx, T dyy, T dzz, T
         m[26] = dxx * Kyy * Kzz + cs2 * (dyy * Kzz + cs2 * dzz) +
                 T(2) * (Kxx * Kyz * Kyz + Kyy * Kxz * Kxz + Kzz * Kxy * Kxy) +
                 T(8) * Kxy * Kxz * Kyz;
-        // z digit: exponent -> velocity
+        // z digit: exponent -> velocity.  Before it, every line (m[i],
+        // m[i + 9], m[i + 18]) holds either its z-exponent-1 entry alone (odd
+        // x+y exponent) or its z-exponent-0 and -2 ones (even), the entries
+        // of odd total order being zero: each line is swept without its
+        // products of zero.
+        {
+            const T uu = uz * uz, a1m = T(2) * uz - T(1), a1p = T(2) * uz + T(1);
+            const T am = uu - uz, a0 = T(1) - uu, ap = uu + uz;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) sweep3(m[i], m[i + 9], m[i + 18], uz, m[i], m[i + 9], m[i + 18]);
+            for (int i = 0; i < 9; ++i) {
+                if (i == 0) {  // the rest-state deviation m[0] is zero too
+                    const T k2 = m[18];
+                    m[0] = T(0.5) * k2;
+                    m[9] = -k2;
+                    m[18] = T(0.5) * k2;
+                } else if (i & 1) {
+                    const T k1 = m[i + 9];
+                    m[i] = T(0.5) * (k1 * a1m);
+                    m[i + 9] = -(T(2) * uz * k1);
+                    m[i + 18] = T(0.5) * (k1 * a1p);
+                } else {
+                    const T k0 = m[i], k2 = m[i + 18];
+                    m[i] = T(0.5) * (k0 * am + k2);
+                    m[i + 9] = k0 * a0 - k2;
+                    m[i + 18] = T(0.5) * (k0 * ap + k2);
+                }
+            }
+        }
         // y digit
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -755,7 +859,7 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
 
     Cell<T> c;
     // FP16 phase-field storage: fp16 order parameters of the cells that read
-    // the phase-field values stored here (see eval_cell16)
+    // the phase-field values stored here (see eval_cell16_paired)
     unsigned gref[P::G::shifted ? Q / 2 : 1];
     eval_cell<D, P>(nb, g.np, ph, p, c, P::G::shifted ? gref : nullptr);
     // Scheduling fences between the phases of the cell update keep the

@@ -21,6 +21,7 @@ struct PhysD {
     double inv_tpb;        // 1 / taubar_phi
     double src_pre;        // 1 - 1/(2 taubar_phi)
     double four_W;         // 4 / W
+    double scl_l, dscl;    // FP16 flow codes' scale rho cs^2 = scl_l + dscl phi
     int visc_interp;
     int collision;         // 0 cumulant, 1 SRT
     int cac_edf;           // phase-field equilibrium: 0 second-order, 1 first-order + correction
