@@ -11,7 +11,11 @@ test_oracle_sampled_reduce):
 * the droplet impact on a thin sheet at its full size, 512 x 512 x 256
   (Sec. 3.4; density ratio 1000, viscosity ratio 15, We 8000, Re 1000,
   D = 64), in FP32 and FP16S, ten steps in (about 60 GB of host memory for
-  the decoded states).
+  the decoded states);
+* a 3-D Rayleigh-Taylor lattice past the 32-bit population offsets,
+  512 x 512 x 304 (27 x 79.7M > 2^31 elements per population array), which
+  takes the per-lane addressing with 64-bit plane offsets and the phi pass
+  instead of the row form and the partial sums, FP32, two steps in.
 
 The oracle starts from the GPU's own decoded state at the sampled cells' level.
 The samples are seeded random cells plus both wall layers.  FP64 and FP32 are
@@ -184,3 +188,29 @@ def test_full_size_splash_one_step_at_sampled_cells(storage):
         assert ef < 2e-6 and eg < 2e-6
     else:
         check_fp16_sampled(case, storage, f, g, got_f, got_g, cells, "3-D splash 512x512x256")
+
+
+def test_lattice_past_32bit_population_offsets_one_step_at_sampled_cells():
+    # 512 x 512 x 304: 79.7M cells, 27 x 79.7M population elements per array,
+    # past 2^31, so the kernels index planes with 64-bit offsets (per-lane
+    # form); host memory for the decoded states about 70 GB at the peak
+    case = inputs.rti3d(nx=512, ny=512, nz=304, amp=0.05 * 512)
+    n = case.params["n"]
+    assert 27 * n[0] * n[1] * n[2] > 2 ** 31
+    s = mplb.Solver(case.params, storage="fp32")
+    s.init(case.phi, case.u, case.p)
+    assert s.phi_partial_rows() == 0  # past the 32-bit offsets: the phi pass
+    s.step(2)
+    f = from_abi(3, s.get_populations(0))
+    g = from_abi(3, s.get_populations(1))
+    s.step(1)
+    cells = sample(n, 1500, seed=5)
+    got_f = s.get_populations(0).reshape(27, -1)[:, cells]
+    got_g = s.get_populations(1).reshape(27, -1)[:, cells]
+    del s
+    po = oracle.params_from_dict(case.params)
+    fo, go = oracle.step_sampled(po, f, g, cells)
+    ef = rel_err(from_abi(3, got_f).T, fo)
+    eg = rel_err(from_abi(3, got_g).T, go)
+    print("3-D 512x512x304 fp32 one step at %d cells: f rel %.2e, g rel %.2e" % (cells.size, ef, eg))
+    assert ef < 2e-6 and eg < 2e-6
