@@ -27,6 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# what a kernel that only loads and stores the update's 54 population planes
+# moves on this part (measured, GB/s): the practical ceiling of the step
+STREAM_CEILING_GBS = 5500.0
 # algorithmic bytes per cell for one launch of each kernel, FP32, D3Q27:
 #   collide: read 27 f' + 27 g + phi, write 27 f' + 27 g  -> 4 * (27 * 4 + 1) = 436
 #   phi:     read 27 g, write phi                          -> 4 * (27 + 1)     = 112
@@ -374,6 +377,75 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_batch_groups(args):
+    """The batch workload's 64 domains one domain per launch, timed group by
+    group of equal edge, against the time each group would take streaming its
+    algorithmic bytes at STREAM_CEILING_GBS (548 B/cell per step with the phi
+    pass, 476 with the phi-summing update, FP32): where plain loses time, a
+    batched form can win it back; elsewhere no form can.  Then the domains of
+    edge 48 and less alone in the batch's shared launches."""
+    import torch
+
+    from paper_2101_06769_amd import inputs, mplb
+
+    steps = args.batch_steps
+    cases = inputs.batch_rti3d(count=args.domains, seed=0, steps=steps)
+    b = mplb.Batch(3, "fp32", capacity=len(cases), max_tiles=1 << 22)
+    b.set_graph_chunk(16)
+    solvers = [mplb.Solver(c.params, storage="fp32", stream=b.stream) for c in cases]
+    edges = [c.params["n"][0] for c in cases]
+    groups, total, bound = [], 0.0, 0.0
+    for e in sorted(set(edges)):
+        idx = [i for i, ee in enumerate(edges) if ee == e]
+        for i in idx:
+            solvers[i].init(cases[i].phi, cases[i].u, cases[i].p)
+        form = solvers[idx[0]].phi_partial_rows() > 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in idx:
+            solvers[i].step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        cells = sum(cases[i].ncells for i in idx)
+        bpc = 476 if form else 548
+        at_ceiling = cells * bpc * steps / (STREAM_CEILING_GBS * 1e9)
+        groups.append({"edge": e, "domains": len(idx), "cells": cells, "plain_s": round(el, 3),
+                       "mlups": round(cells * steps / el / 1e6, 1),
+                       "step_form": "phi-summing update" if form else "phi pass",
+                       "bytes_per_cell": bpc, "s_at_ceiling": round(at_ceiling, 3)})
+        total += el
+        bound += min(at_ceiling, el)
+    small = [i for i, e in enumerate(edges) if e <= 48]
+    b.set_solo_cells(1 << 62)
+
+    def attach_small():
+        for i in small:
+            solvers[i].init(cases[i].phi, cases[i].u, cases[i].p)
+        return [b.attach(solvers[i], steps) for i in small]
+
+    slots = attach_small()
+    b.step(16)  # captures the chunk graph
+    for sl in slots:
+        b.detach(sl)
+    slots = attach_small()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    t_small = time.perf_counter() - t0
+    for sl in slots:
+        b.detach(sl)
+    print(json.dumps({
+        "workload": "batch mix one domain per launch, by edge, %d steps" % steps,
+        "groups": groups, "plain_total_s": round(total, 3),
+        "best_any_form_s": round(bound, 3),
+        "max_speedup_vs_plain": round(total / bound, 3),
+        "stream_ceiling_GBs": STREAM_CEILING_GBS,
+        "edge_le_48_shared_launches_s": round(t_small, 3),
+        "edge_le_48_plain_s": round(sum(g["plain_s"] for g in groups if g["edge"] <= 48), 3)}),
+        flush=True)
+
+
 def splash_vs_oracle(storage):
     """Per-field max errors against the FP64 oracle of the same droplet impact
     on a reduced lattice (128 x 128 x 64, D = 16, 500 steps; the oracle's
@@ -712,12 +784,13 @@ def main():
                          "phi pass over the pulled populations every step")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="rti3d",
-                    choices=["rti3d", "rti2d", "batch", "serve", "splash", "rti2d_convergence",
-                             "stability", "splash2d", "edf"],
+                    choices=["rti3d", "rti2d", "batch", "batch_groups", "serve", "splash",
+                             "rti2d_convergence", "stability", "splash2d", "edf"],
                     help="rti3d: the 128x128x512 step (default); rti2d: one 2-D Rayleigh-Taylor "
                          "domain of --n2d squared cells (the largest served size); batch: 64 "
                          "uneven domains, "
-                         "batched vs one per launch; serve: request replay; splash: "
+                         "batched vs one per launch; batch_groups: the same mix one domain per "
+                         "launch, timed edge by edge; serve: request replay; splash: "
                          "512x512x256 droplet impact in FP64 / FP32 / FP16")
     ap.add_argument("--n2d", type=int, default=1024, help="rti2d: cells per side")
     ap.add_argument("--splash-steps", type=int, default=200)
@@ -748,6 +821,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "batch_groups":
+        return bench_batch_groups(args)
     if args.workload == "serve":
         return bench_serve(args)
     if args.workload == "splash":
