@@ -824,7 +824,9 @@ int mplb_load(mplb_solver *s, const void *host_blob, size_t bytes)
         return fail(MPLB_EINVAL, "not a saved state of this library version");
     if (h.param_hash != param_hash(s->prm))
         return fail(MPLB_EINVAL, "saved state belongs to other parameters");
-    if (h.nregions > SAVE_MAX_REGIONS || (h.cur != 0 && h.cur != 1) || h.steps < 0)
+    if (h.nregions > SAVE_MAX_REGIONS || (h.cur != 0 && h.cur != 1) || h.steps < 0 ||
+        (h.nphi != 0 && h.nphi != 1) || h.block[0] < 1 || h.block[1] < 1 || h.block[2] < 1 ||
+        (long long)h.block[0] * h.block[1] * h.block[2] > 256)
         return fail(MPLB_EINVAL, "corrupt saved state header");
     uint64_t sizes[SAVE_MAX_REGIONS];
     std::memcpy(sizes, in + sizeof(h) + sizeof(mplb_params), sizeof(sizes));

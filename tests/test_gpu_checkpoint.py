@@ -79,6 +79,15 @@ def test_load_rejects_other_parameters_and_truncated_blobs():
     with pytest.raises(mplb.MplbError) as e:
         fresh.load(b"x" * len(blob))
     assert e.value.code == mplb.EINVAL
+    # a header whose launch block is corrupt (the saved block shape, three
+    # int32 after magic, format, region count, parameter hash, step count and
+    # five int32 of bookkeeping: bytes 52..63) is refused, not launched
+    bad = bytearray(blob)
+    bad[52:56] = (0).to_bytes(4, "little")
+    with pytest.raises(mplb.MplbError) as e:
+        fresh.load(bytes(bad))
+    assert e.value.code == mplb.EINVAL
+    fresh.load(blob)  # the intact blob still loads
 
 
 def test_attached_solver_refuses_solo_calls():
