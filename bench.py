@@ -95,6 +95,16 @@ def profiled_traffic(storage, workload, kernel):
     return rec["traffic_bytes_per_launch"]
 
 
+def device_info():
+    """The GPU the line was measured on (boxes of the same part differ by a few
+    percent in streaming rate, so the line names its device)."""
+    import torch
+
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": p.gcnArchName, "compute_units": p.multi_processor_count,
+            "hbm_GiB": round(p.total_memory / 2 ** 30, 1), "pci_bus_id": p.pci_bus_id}
+
+
 def cpu_model():
     """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
     import subprocess
@@ -525,6 +535,8 @@ def bench_splash(args):
         if storage != "fp64_floor":
             rec["vs_fp64_oracle_reduced"] = splash_vs_oracle(storage)
         out[storage] = rec
+        print("splash: %s, %d steps in %.1f s" % (storage, args.splash_steps, ms / 1e3),
+              file=sys.stderr, flush=True)
         del s, f
         torch.cuda.empty_cache()
     line = {
@@ -931,6 +943,7 @@ def main():
         "method_frac": round(method_bytes * N * args.steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "phase_mass_rel_drift": abs(red[0] - m0) / m0,
         "status": "ok" if rc == mplb.OK else "unstable",
+        "device": device_info(),
     }
     del s
     if not args.no_cpu_baseline and dim == 3:
