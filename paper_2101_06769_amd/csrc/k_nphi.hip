@@ -33,6 +33,7 @@ template <class P>
 __global__ void __launch_bounds__(256) k_phi_merge(Geom g, Ptrs p, NextPhi q)
 {
     using T = typename P::T;
+    constexpr int MERGE_Z = merge_planes<P>();
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = __builtin_amdgcn_readfirstlane(int(blockIdx.y * 4 + threadIdx.y));
     const int z0 = int(blockIdx.z) * MERGE_Z;
@@ -123,8 +124,9 @@ hipError_t launch_collide_nphi(const Ctx &c, const NextPhi &q)
 hipError_t launch_phi_merge(const Ctx &c, const NextPhi &q)
 {
     if (!nphi_tile_ok(c, q)) return hipErrorInvalidValue;
-    const dim3 grid(c.g.nx / 64, (c.g.ny + 3) / 4, (c.g.nz + MERGE_Z - 1) / MERGE_Z);
     return dispatch(c, [&]<int D, class P>() {
+        constexpr int MERGE_Z = merge_planes<P>();
+        const dim3 grid(c.g.nx / 64, (c.g.ny + 3) / 4, (c.g.nz + MERGE_Z - 1) / MERGE_Z);
         hipLaunchKernelGGL((k_phi_merge<P>), grid, dim3(64, 4, 1), 0, c.stream, c.g,
                            c.p, q);
         return hipGetLastError();
