@@ -1309,14 +1309,15 @@ __device__ __forceinline__ T nphi_merge_sum(const Geom &g, const T (&v)[3][3], i
 
 // Block (64, 4): each wavefront is 64 cells of one row, so y, z and every
 // index but x are wavefront-uniform; each thread merges merge_planes<P>()
-// planes, all loads issued before the sums: four in FP32 and FP64, two in
+// planes, all loads issued before the sums: four in FP32, two in FP64 and in
 // the FP16 formats, whose merge also copies the 4-byte references into the
-// 8-byte records (measured per format: FP32 37.1 us with four against 39.9 with
-// two and 40.7 with eight planes; FP16S_ALL 72.3 us with two against 74.8 and 86.1).
+// 8-byte records (measured per format: FP32 37.1 us with four against 39.9
+// with two and 40.7 with eight planes; FP16S_ALL 72.3 us with two against
+// 74.8 and 86.1; FP64 88.6 us with two against 90.0 with four).
 template <class P>
 constexpr int merge_planes()
 {
-    return P::F::shifted ? 2 : 4;
+    return (P::F::shifted || sizeof(typename P::T) == 8) ? 2 : 4;
 }
 
 // phi of cell (x, y, z) from its pieces, loaded one by one (batched form).
