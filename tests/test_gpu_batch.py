@@ -216,3 +216,31 @@ def test_nonfinite_domain_stepping_alone_is_flagged():
     st = b.status()
     assert st[sb] == mplb.EUNSTABLE and st[so] == mplb.OK
     assert b.remaining(sb) == 0  # retired
+
+
+@pytest.mark.parametrize("storage,chunk", [("fp64", 0), ("fp32", 4), ("fp16s", 4), ("fp16s_all", 0),
+                                           ("fp16s_all", 4)])
+def test_2d_batch_equals_alone_bitwise_in_every_format(storage, chunk):
+    # uneven 2-D domains (ragged sizes, walls and symmetry planes, a drop at
+    # density ratio 1000 beside Rayleigh-Taylor cells) in the shared 2-D
+    # launches: each the same bits as alone
+    cases = [inputs.rti2d(nx=37, ny=52, amp=2.0),
+             inputs.rti2d(nx=64, ny=128, amp=3.0),
+             inputs.impacting_droplet2d(n=96),
+             inputs.static_droplet(dim=2, n=(50, 44, 1), R=9.0, sigma=1e-3, rho_ratio=1000.0)]
+    steps = 21
+    alone = []
+    for c in cases:
+        s = solver_for(c, storage)
+        s.step(steps)
+        alone.append(state(s))
+    b = mplb.Batch(2, storage, capacity=4, max_tiles=1 << 14)
+    b.set_graph_chunk(chunk)
+    solvers = [solver_for(c, storage, stream=b.stream) for c in cases]
+    for s in solvers:
+        b.attach(s, steps)
+    b.step(steps + 4)
+    for k, (s, (fa, ga)) in enumerate(zip(solvers, alone)):
+        fb, gb = state(s)
+        assert s.steps_done() == steps
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), (storage, k)
