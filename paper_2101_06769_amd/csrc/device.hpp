@@ -596,13 +596,16 @@ __device__ __forceinline__ void eval_cell(const NB &nb, long long np,
 
 // One 3-point sweep: central moments (k0, k1, k2) about u of a set on the
 // velocities {-1, 0, +1} -> the three values.
+// Written as its even and odd parts in u, E = (k0 u^2 + k2)/2 + k1 u and
+// O = (k0 u + k1)/2: vm = E - O, v0 = k0 - 2E, vp = E + O.
 template <typename T>
 __device__ __forceinline__ void sweep3(T k0, T k1, T k2, T u, T &vm, T &v0, T &vp)
 {
-    const T uu = u * u;
-    vm = T(0.5) * (k0 * (uu - u) + k1 * (T(2) * u - T(1)) + k2);
-    v0 = k0 * (T(1) - uu) - T(2) * u * k1 - k2;
-    vp = T(0.5) * (k0 * (uu + u) + k1 * (T(2) * u + T(1)) + k2);
+    const T E = k0 * (T(0.5) * (u * u)) + (k1 * u + T(0.5) * k2);
+    const T O = k0 * (T(0.5) * u) + T(0.5) * k1;
+    vm = E - O;
+    v0 = k0 - T(2) * E;
+    vp = E + O;
 }
 
 // Post-collision unit-mass set from velocity and relaxed second-order central
