@@ -324,6 +324,30 @@ __device__ __forceinline__ R own_at(const NbRow &n, const R *base)
 __device__ __forceinline__ unsigned short half_bits(float v) { return __half_as_ushort(__float2half(v)); }
 __device__ __forceinline__ float half_val(unsigned short b) { return __half2float(__ushort_as_half(b)); }
 
+// Stores the FP16 code of direction plane `plane` at the cell (row + x) of a
+// population array, non-temporally: the next update reads it a launch later,
+// and cached, the written lines were written back to HBM during the next
+// order-parameter merge (FP16S_ALL merge 72.2 -> 57.9 us, step 0.604 -> 0.582
+// ms on 128 x 128 x 512).  BUF (row form): through a buffer resource with
+// the row as scalar offset and the column as per-lane offset, which leaves
+// the 64-bit address arithmetic of the store to the scalar unit; taken where
+// instruction issue bounds the update (both sets in FP16: 0.582 -> 0.577 ms;
+// the FP16 flow set alone measured 0.642 against 0.645 ms without it).
+template <bool BUF, class NB>
+__device__ __forceinline__ void store_code(const NB &, void *base, long long plane, int row, int x,
+                                           unsigned short bits)
+{
+    if constexpr (BUF && std::is_same<NB, NbRow>::value) {
+        // raw buffer (stride 0) without a range limit; word 3 as gfx9 takes it for
+        // untyped accesses; cache policy 2: non-temporal
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            static_cast<unsigned short *>(base) + plane, 0, -1, 0x00020000);
+        __builtin_amdgcn_raw_buffer_store_b16(bits, r, unsigned(x) * 2u, unsigned(row) * 2u, 2);
+    } else {
+        __builtin_nontemporal_store(bits, lane_ptr(static_cast<unsigned short *>(base), plane + row, x));
+    }
+}
+
 // ------------------------------------------------------------- cell state
 template <typename T>
 struct Cell {
@@ -893,8 +917,7 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
                 const float w = weight<D, float>(a);
                 const __half h = __float2half((dev * (1.0f / w) + (c.pstar - W.P)) * isw);
                 fsum += dec_f16(w, W, sw, __half2float(h));
-                *lane_ptr(static_cast<__half *>(p.Fout), (long long)a * g.np + row, xl) =
-                    __half_as_ushort(h);
+                store_code<P::G::shifted>(nb, p.Fout, (long long)a * g.np, row, xl, __half_as_ushort(h));
             } else {
                 const T v = dev + weight<D, T>(a) * c.pstar;
                 fsum += v;
@@ -997,7 +1020,8 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
                     emit(a, dev);
             }
         }
-        if constexpr (P::F::shifted) *lane_ptr(p.ref, row, xl) = rw;
+        // non-temporal, as the codes: the order-parameter stage reads it a launch later
+        if constexpr (P::F::shifted) __builtin_nontemporal_store(rw, lane_ptr(p.ref, row, xl));
     };
 
     // --- phase field (Sec. 2.2)
@@ -1021,8 +1045,7 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
                 const __half h = __float2half(gout * (1.0f / w) - F);
                 const float dec = dec_g16(w, F, __half2float(h));
                 gsum += dec;
-                *lane_ptr(static_cast<__half *>(p.Gout), (long long)a * g.np + row, xl) =
-                    __half_as_ushort(h);
+                store_code<P::G::shifted>(nb, p.Gout, (long long)a * g.np, row, xl, __half_as_ushort(h));
                 if constexpr (KEEP) keep[nphi_slot(a) * kstride] = dec;
             } else {
                 gsum += gout;
@@ -1043,9 +1066,10 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
                     dy = qy - *lane_ptr(in, g.np + row, xl);
                     dz = qz - *lane_ptr(in, 2 * g.np + row, xl);
                 }
-                *lane_ptr(out, row, xl) = qx;
-                *lane_ptr(out, g.np + row, xl) = qy;
-                *lane_ptr(out, 2 * g.np + row, xl) = qz;
+                // non-temporal: read by the next update
+                __builtin_nontemporal_store(qx, lane_ptr(out, row, xl));
+                __builtin_nontemporal_store(qy, lane_ptr(out, g.np + row, xl));
+                __builtin_nontemporal_store(qz, lane_ptr(out, 2 * g.np + row, xl));
             }
             // the pulled values: all loads issued before the first store (the
             // compiler cannot prove the stored set apart from the pulled one,
