@@ -148,24 +148,35 @@ __device__ __forceinline__ PullLoc pull_loc(const NbRow &n, int a)
     return l;
 }
 
-// Element (plane offset + location) of a device array, global access.
-template <typename R>
+// Element (plane offset + location) of a device array, global access.  NT:
+// a non-temporal load (the value is read once, by this cell).
+template <bool NT = false, typename R>
 __device__ __forceinline__ R load_loc(const NbLane &, const R *base, long long plane,
                                       const PullLoc &l)
 {
-    return gld(base, plane + l.rs);
+    if constexpr (NT)
+        return __builtin_nontemporal_load(&((gptr<const R>)base)[plane + l.rs]);
+    else
+        return gld(base, plane + l.rs);
 }
-template <typename R>
+template <bool NT = false, typename R>
 __device__ __forceinline__ R load_loc(const NbRow &, const R *base, long long plane,
                                       const PullLoc &l)
 {
-    return *lane_ptr(base, plane + l.rs, l.xs);
+    if constexpr (NT)
+        return __builtin_nontemporal_load(lane_ptr(base, plane + l.rs, l.xs));
+    else
+        return *lane_ptr(base, plane + l.rs, l.xs);
 }
-template <class NB>
+// An FP16 code, as a float.  NT: non-temporal load, taken where both sets are
+// FP16 (FP16S_ALL update 521 -> 501 us on 128 x 128 x 512; with the flow set
+// alone in FP16, or in FP32 and FP64, non-temporal pulls measured slower:
+// FP16S 586 -> 613, FP32 683 -> 702 us).
+template <bool NT = false, class NB>
 __device__ __forceinline__ float load_code(const NB &n, const void *base, long long plane,
                                            const PullLoc &l)
 {
-    const unsigned short c = load_loc(n, static_cast<const unsigned short *>(base), plane, l);
+    const unsigned short c = load_loc<NT>(n, static_cast<const unsigned short *>(base), plane, l);
     return __half2float(__ushort_as_half(c));
 }
 
@@ -502,8 +513,8 @@ __device__ __forceinline__ void eval_cell16_paired(const NB &nb, long long np, c
         lap += w * ((pp - p0) + (pm - p0));
         if (gref) gref[a - (Q / 2 + 1)] = unsigned(half_bits(pp)) | (unsigned(half_bits(pm)) << 16);
         const PullLoc la = pull_loc<D>(nb, a), lb = pull_loc<D>(nb, b);
-        const float qa = load_code(nb, p.Fin, (long long)la.dir * np, la);
-        const float qb = load_code(nb, p.Fin, (long long)lb.dir * np, lb);
+        const float qa = load_code<true>(nb, p.Fin, (long long)la.dir * np, la);
+        const float qb = load_code<true>(nb, p.Fin, (long long)lb.dir * np, lb);
         // the reference words selected as integers: no branch on the
         // (wavefront-uniform in the row form) bounce-back flags
         const Ref16 ra = unpack_ref(la.bb ? own_bits : rec_ref(rm));
@@ -842,8 +853,8 @@ __device__ __forceinline__ typename P::T phi_body(const NB &nb, long long np, co
         for (int a = Q / 2 + 1; a < Q; ++a) {
             const int b = opposite<D>(a);
             const PullLoc la = pull_loc<D>(nb, a), lb = pull_loc<D>(nb, b);
-            m += dec_g16(weight<D, float>(a), F, load_code(nb, p.Gin, (long long)la.dir * np, la));
-            m += dec_g16(weight<D, float>(b), F, load_code(nb, p.Gin, (long long)lb.dir * np, lb));
+            m += dec_g16(weight<D, float>(a), F, load_code<true>(nb, p.Gin, (long long)la.dir * np, la));
+            m += dec_g16(weight<D, float>(b), F, load_code<true>(nb, p.Gin, (long long)lb.dir * np, lb));
         }
         s = own_at(nb, p.grest_in) + m;
     } else {
@@ -1083,7 +1094,7 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
                     if constexpr (P::G::shifted) {
                         const PullLoc l = pull_loc<D>(nb, a);
                         pre[a] = dec_g16(weight<D, float>(a), c.Fown,
-                                         load_code(nb, p.Gin, (long long)l.dir * g.np, l));
+                                         load_code<true>(nb, p.Gin, (long long)l.dir * g.np, l));
                     } else {
                         pre[a] = pull<D, typename P::G, T>(nb, p.Gin, g.np, a);
                     }
