@@ -53,9 +53,10 @@ __global__ void __launch_bounds__(256) k_phi_merge(Geom g, Ptrs p, NextPhi q)
             const int zs = z - oz;
             const bool ok = z < g.nz && !(wz && (zs < 0 || zs >= g.nz));
             const long long row = (long long)(z * g.ny + y) * g.nx;
-            v[k][oz + 1][0] = ok ? *lane_ptr(part, (oz + 1) * g.np + row, x) : T(0);
-            v[k][oz + 1][1] = ok && first ? *lane_ptr(edge, nphi_edge_at(g, ntiles, 0, oz, t, z, 0), x) : T(0);
-            v[k][oz + 1][2] = ok && last ? *lane_ptr(edge, nphi_edge_at(g, ntiles, 1, oz, t, z, 0), x) : T(0);
+            // every partial sum and edge value is read once: non-temporal
+            v[k][oz + 1][0] = ok ? __builtin_nontemporal_load(lane_ptr(part, (oz + 1) * g.np + row, x)) : T(0);
+            v[k][oz + 1][1] = ok && first ? __builtin_nontemporal_load(lane_ptr(edge, nphi_edge_at(g, ntiles, 0, oz, t, z, 0), x)) : T(0);
+            v[k][oz + 1][2] = ok && last ? __builtin_nontemporal_load(lane_ptr(edge, nphi_edge_at(g, ntiles, 1, oz, t, z, 0), x)) : T(0);
         }
     }
 #pragma unroll
