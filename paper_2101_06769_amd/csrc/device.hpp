@@ -369,6 +369,9 @@ struct Cell {
     T Fown;  // FP16 formats: the cell's own reference order parameter (fp16)
 };
 
+// LDS slot of a moving D3Q27 direction (the rest direction, 13, has none).
+__host__ __device__ constexpr int nphi_slot(int a) { return a < 13 ? a : a - 1; }
+
 // grad(phi) = (1/cs^2) sum_a w_a c_a phi(x + c_a);
 // lap(phi) = (2/cs^2) sum_a w_a [phi(x + c_a) - phi(x)]   (Sec. 2.2)
 // Summed over pairs of opposite directions, w (phi(x+c) - phi(x-c)) and
@@ -420,14 +423,19 @@ __device__ __forceinline__ void closure(const Phys<T> &ph, Cell<T> &c)
 // Raw moments of the pulled flow populations (orders 0..2), accumulated over
 // pairs of opposite directions (f_a + f_opp for even moments, f_a - f_opp for
 // odd ones) so that the pressure part w p cancels exactly in the odd moments
-// and the velocity part cancels before it reaches the even ones.
-template <int D, class P, class NB>
+// and the velocity part cancels before it reaches the even ones.  STASH
+// (D3Q27): the pulled values are also kept for a collision that needs them
+// one by one, the moving ones in stash[nphi_slot(a) * sstride], the rest
+// value in *stash_rest.
+template <int D, class P, bool STASH, class NB>
 __device__ __forceinline__ void flow_moments(const NB &nb, long long np, const Ptrs &p,
-                                             Cell<typename P::T> &c)
+                                             Cell<typename P::T> &c, typename P::T *stash,
+                                             int sstride, typename P::T *stash_rest)
 {
     using T = typename P::T;
     constexpr int Q = Lat<D>::Q;
     T S0 = pull<D, typename P::F, T>(nb, p.Fin, np, Q / 2);
+    if constexpr (STASH) *stash_rest = S0;
     T Sx = 0, Sy = 0, Sz = 0, Sxx = 0, Syy = 0, Szz = 0, Sxy = 0, Sxz = 0, Syz = 0;
 #pragma unroll
     for (int a = Q / 2 + 1; a < Q; ++a) {
@@ -435,6 +443,10 @@ __device__ __forceinline__ void flow_moments(const NB &nb, long long np, const P
         const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
         const T va = pull<D, typename P::F, T>(nb, p.Fin, np, a);
         const T vb = pull<D, typename P::F, T>(nb, p.Fin, np, b);
+        if constexpr (STASH) {
+            stash[nphi_slot(a) * sstride] = va;
+            stash[nphi_slot(b) * sstride] = vb;
+        }
         const T sp = va + vb, dm = va - vb;
         S0 += sp;
         if (cx) { Sx += T(cx) * dm; Sxx += sp; }
@@ -542,14 +554,16 @@ __device__ __forceinline__ void eval_cell16_paired(const NB &nb, long long np, c
 
 }
 
-template <int D, class P, class NB>
+template <int D, class P, bool STASH, class NB>
 __device__ __forceinline__ void eval_cell16_hoisted(const NB &nb, long long np, const Phys<float> &ph,
-                                            const Ptrs &p, Cell<float> &c, unsigned *gref)
+                                            const Ptrs &p, Cell<float> &c, unsigned *gref,
+                                            float *stash, int sstride, float *stash_rest)
 {
     constexpr int Q = Lat<D>::Q, H = Q / 2;
     const unsigned long long *rec = static_cast<const unsigned long long *>(p.phi);
     const unsigned long long r0 = phi_at(nb, rec, 0, 0, 0);
     const float frest = own_at(nb, p.frest_in);
+    if constexpr (STASH) *stash_rest = frest;
     unsigned long long rp[H], rm[H];
     unsigned short qa_bits[H], qb_bits[H];
     auto load_pair = [&](int a) {
@@ -590,6 +604,10 @@ __device__ __forceinline__ void eval_cell16_hoisted(const NB &nb, long long np, 
         const Ref16 rb = unpack_ref(lb.bb ? own_bits : rec_ref(rp[k]));
         const float va = dec_f16(w, ra, flow_scale16(ph, ra.F), qa);
         const float vb = dec_f16(w, rb, flow_scale16(ph, rb.F), qb);
+        if constexpr (STASH) {
+            stash[nphi_slot(a) * sstride] = va;
+            stash[nphi_slot(b) * sstride] = vb;
+        }
         const float sp = va + vb, dm = va - vb;
         S0 += sp;
         if (cx) { Sx += float(cx) * dm; Sxx += sp; }
@@ -610,21 +628,26 @@ __device__ __forceinline__ void eval_cell16_hoisted(const NB &nb, long long np, 
     velocity<D, float>(c);
 }
 
-template <int D, class P, class NB>
+// STASH (D3Q27, not where both sets are FP16): the pulled flow values,
+// decoded, are also kept as flow_moments describes.
+template <int D, class P, bool STASH = false, class NB>
 __device__ __forceinline__ void eval_cell(const NB &nb, long long np,
                                           const Phys<typename P::T> &ph, const Ptrs &p,
-                                          Cell<typename P::T> &c, unsigned *gref = nullptr)
+                                          Cell<typename P::T> &c, unsigned *gref = nullptr,
+                                          typename P::T *stash = nullptr, int sstride = 0,
+                                          typename P::T *stash_rest = nullptr)
 {
     using T = typename P::T;
     if constexpr (P::F::shifted) {
+        static_assert(!(STASH && P::G::shifted), "no stash where both sets are FP16");
         if constexpr (P::G::shifted)
             eval_cell16_paired<D, P>(nb, np, ph, p, c, gref);
         else
-            eval_cell16_hoisted<D, P>(nb, np, ph, p, c, gref);
+            eval_cell16_hoisted<D, P, STASH>(nb, np, ph, p, c, gref, stash, sstride, stash_rest);
     } else {
         stencil<D, T>(nb, static_cast<const T *>(p.phi), c);
         closure<D, T>(ph, c);
-        flow_moments<D, P>(nb, np, p, c);
+        flow_moments<D, P, STASH>(nb, np, p, c, stash, sstride, stash_rest);
         velocity<D, T>(c);
     }
 }
@@ -881,8 +904,6 @@ __device__ __forceinline__ typename P::T phi_cell(const Geom &g, const Ptrs &p, 
 // phase-field values are also written to keep[nphi_slot(a) * kstride] (LDS),
 // the rest direction's to *keep_rest, for the
 // partial sums of the next order parameter.
-// LDS slot of a moving D3Q27 direction (the rest direction, 13, has none).
-__host__ __device__ constexpr int nphi_slot(int a) { return a < 13 ? a : a - 1; }
 
 template <int D, class P, int COLL, class NB, bool KEEP = false>
 __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
@@ -899,7 +920,13 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
     // FP16 phase-field storage: fp16 order parameters of the cells that read
     // the phase-field values stored here (see eval_cell16_paired)
     unsigned gref[P::G::shifted ? Q / 2 : 1];
-    eval_cell<D, P>(nb, g.np, ph, p, c, P::G::shifted ? gref : nullptr);
+    // single relaxation time needs the pulled flow values one by one: where
+    // the LDS slots of the stored phase-field values are free until the flow
+    // collision (the flow set collides first), the moment pass leaves them
+    // there instead of the collision pulling them from memory again
+    constexpr bool STASH = KEEP && (COLL & 1) && D == 3 && !P::G::shifted;
+    eval_cell<D, P, STASH>(nb, g.np, ph, p, c, P::G::shifted ? gref : nullptr, keep, kstride,
+                           keep_rest);
     // Scheduling fences between the phases of the cell update keep the
     // compiler from hoisting every load of the kernel to its start, which
     // would hold them all in registers at once (spills, lower occupancy).
@@ -1004,7 +1031,9 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
             for (int a = 0; a < Q; ++a) {
                 const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
                 T v;
-                if constexpr (P::F::shifted) {
+                if constexpr (STASH) {
+                    v = a == Q / 2 ? *keep_rest : keep[nphi_slot(a) * kstride];
+                } else if constexpr (P::F::shifted) {
                     // decode with the writer's reference, from its record
                     const unsigned long long *rec = static_cast<const unsigned long long *>(p.phi);
                     if (a == Q / 2) {

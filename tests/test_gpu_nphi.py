@@ -10,8 +10,10 @@ whole rows by as many rows as 512 threads (256 with FP64) allow, dividing
 ny, whatever the block of the other kernels).  Cases cover tiles of one to
 eight rows, walls and periodic wrap in y and z, one-tile-high lattices (the
 edge sums wrap onto the same tile), the transitions that must fall back to
-the pull sum (first step, a step without partial sums), and the batched
-form, which sums phi the same way and must give the same bits."""
+the pull sum (first step, a step without partial sums), the batched
+form, which sums phi the same way and must give the same bits, and the
+single-relaxation-time collision, whose summing update keeps the pulled flow
+values in LDS instead of pulling them twice."""
 import numpy as np
 import pytest
 
@@ -178,7 +180,41 @@ def test_first_order_equilibrium_with_partial_sums():
     assert rel_err(from_abi(3, s.get_populations(1)), g3) < 1e-12
 
 
-def nphi_batch_cases(storage_seed=0, wide=False):
+# Single relaxation time (the ablation of Sec. 4) relaxes every moment, so its
+# collision needs the pulled flow values one by one, not only their moments:
+# the summing update keeps them in the LDS slots of its phase-field values
+# between the moment pass and the flow collision (where the flow set collides
+# first), the pull-sum update pulls them again.  Several steps, so that the
+# summing update runs after the first (pull-sum) step.
+@pytest.mark.parametrize("n,bc", [CASES[0], CASES[2], CASES[3], CASES[7], CASES[9]])
+def test_single_relaxation_time_with_partial_sums_matches_oracle_fp64(n, bc):
+    params, phi, u, p = random_case(3, n, bc, seed=sum(n) + 7, collision=1)
+    po, f, g = noisy_state(params, phi, u, p, seed=9, amp=0.03)
+    s = run(params, "fp64", (f, g), (phi, u, p), 0, 1)
+    assert s.uses_phi_partials()
+    s.step(4)
+    f4, g4 = oracle.step(po, f, g, 4)
+    ef = rel_err(from_abi(3, s.get_populations(0)), f4)
+    eg = rel_err(from_abi(3, s.get_populations(1)), g4)
+    print("partial phi srt fp64 %s %s: f' %.2e g %.2e" % (n, bc, ef, eg))
+    assert ef < 1e-12 and eg < 1e-12, (ef, eg)
+
+
+@pytest.mark.parametrize("storage,tol", [("fp32", 2e-5), ("fp16s", 1e-3), ("fp16s_all", 1e-3)])
+def test_single_relaxation_time_partial_sums_match_pull_sum(storage, tol):
+    params, phi, u, p = random_case(3, (128, 8, 5), (0, 1, 1), seed=77, collision=1)
+    out = []
+    for mode in (1, 0):
+        s = run(params, storage, None, (phi, u, p), 6, mode)
+        assert s.uses_phi_partials() == bool(mode)
+        out.append((s.get_populations(0), s.get_populations(1), s.fields()["phi"]))
+    for k in range(3):
+        e = rel_err(out[0][k], out[1][k])
+        print("srt partial vs pull %s [%d]: %.2e" % (storage, k, e))
+        assert e < tol, (k, e)
+
+
+def nphi_batch_cases(storage_seed=0, wide=False, collision=0):
     # x-periodic domains whose update sums phi (rows of 64 / 128 / 192 cells,
     # and 512 with wide) beside ones that do not (48-wide rows), walls and
     # periodic wrap in y, z
@@ -188,7 +224,7 @@ def nphi_batch_cases(storage_seed=0, wide=False):
         spec.append(((512, 2, 3), (0, 1, 1)))
     out = []
     for k, (n, bc) in enumerate(spec):
-        params, phi, u, p = random_case(3, n, bc, seed=100 + k + storage_seed)
+        params, phi, u, p = random_case(3, n, bc, seed=100 + k + storage_seed, collision=collision)
         out.append((params, phi, u, p))
     return out
 
@@ -200,11 +236,12 @@ def batch_solver(case, storage, stream):
     return s
 
 
-@pytest.mark.parametrize("storage,chunk", [("fp32", 0), ("fp32", 4), ("fp64", 4), ("fp16s", 4),
-                                           ("fp16s_all", 4)])
-def test_batch_with_phi_summing_domains_equals_alone_bitwise(storage, chunk):
+@pytest.mark.parametrize("storage,chunk,collision", [
+    ("fp32", 0, 0), ("fp32", 4, 0), ("fp64", 4, 0), ("fp16s", 4, 0), ("fp16s_all", 4, 0),
+    ("fp32", 4, 1), ("fp64", 0, 1), ("fp16s", 4, 1), ("fp16s_all", 0, 1)])
+def test_batch_with_phi_summing_domains_equals_alone_bitwise(storage, chunk, collision):
     wide = storage == "fp32"
-    cases = nphi_batch_cases(wide=wide)
+    cases = nphi_batch_cases(wide=wide, collision=collision)
     steps = 7
     alone = []
     for c in cases:
