@@ -794,6 +794,12 @@ def main():
                     help="1: the update sums the next phi from the values it stores and the "
                          "next step merges the partial sums (default, where it applies); 0: a "
                          "phi pass over the pulled populations every step")
+    ap.add_argument("--collision", default="cumulant", choices=["cumulant", "srt"],
+                    help="rti3d / rti2d: the flow collision (srt: single relaxation time, the "
+                         "ablation of Sec. 4)")
+    ap.add_argument("--cac-edf", type=int, default=0, choices=[0, 1],
+                    help="rti3d / rti2d: 1 takes the first-order phase-field equilibrium with "
+                         "its correction term (Sec. 2.2), which keeps the previous (phi u) per cell")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="rti3d",
                     choices=["rti3d", "rti2d", "batch", "batch_groups", "serve", "splash",
@@ -876,6 +882,15 @@ def main():
         label = ("3-D Rayleigh-Taylor, D3Q27 cumulant + D3Q27 Allen-Cahn, 128x128x%d, At 0.5, "
                  "Re 1000, W 5, %s storage" % (args.nz, args.storage))
         wtag = "rti3d_128x128x%d" % args.nz
+    variant = ""
+    if args.collision == "srt":
+        case.params["collision"] = mplb.COLL_SRT
+        label += ", SRT collision"
+        variant += "_srt"
+    if args.cac_edf:
+        case.params["cac_edf"] = 1
+        label += ", first-order phase-field equilibrium"
+        variant += "_edf"
     dim = case.params["dim"]
     N = case.ncells
     s = mplb.Solver(case.params, storage=args.storage)
@@ -901,13 +916,16 @@ def main():
     red, rc = s.reduce()
     m0 = float(case.phi.sum())
     ab = ALG_BYTES[(args.storage, dim)]
+    # the first-order equilibrium reads and writes the previous (phi u), three
+    # values per cell in the arithmetic type
+    hist = 6 * (8 if args.storage == "fp64" else 4) if args.cac_edf else 0
     rows = s.phi_partial_rows()
     if rows:
         kernel, phi_kernel = "k_collide_nphi", "k_phi_merge"
-        kbytes = nphi_bytes(args.storage, rows)[0]
+        kbytes = nphi_bytes(args.storage, rows)[0] + hist
     else:
-        kernel, kbytes, phi_kernel = "k_collide", ab["collide"], "k_phi"
-    method_bytes = ab["method"]
+        kernel, kbytes, phi_kernel = "k_collide", ab["collide"] + hist, "k_phi"
+    method_bytes = ab["method"] + hist
     t_col = ms_col / args.steps / 1e3
     # roofline of the dominant kernel on the method's algorithmic bytes per
     # cell (read and write every population once, write and read phi once);
@@ -932,7 +950,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(args.storage, wtag, kernel),
+                     "traffic": profiled_traffic(args.storage + variant, wtag, kernel),
                      "kernel": kernel, "alg_bytes_per_cell": method_bytes,
                      "kernel_bytes_per_cell": kbytes,
                      "kernel_frac": round(kbytes * N / t_col / 1e9 / HBM_PEAK_GBS, 4),
@@ -946,7 +964,9 @@ def main():
         "device": device_info(),
     }
     del s
-    if not args.no_cpu_baseline and dim == 3:
+    # the oracle leg belongs to the default method's line (a variant's line is
+    # compared with the default one, on the same box)
+    if not args.no_cpu_baseline and dim == 3 and not variant:
         slab = lambda nz: inputs.rti3d(nz=nz, amp=0.05 * 128)  # noqa: E731
         cpu, ref = cpu_baseline(slab, args.cpu_seconds)
         cpu["gpu_speedup"] = round(mlups / cpu["value"], 1)
