@@ -369,7 +369,8 @@ struct Cell {
     T Fown;  // FP16 formats: the cell's own reference order parameter (fp16)
 };
 
-// LDS slot of a moving D3Q27 direction (the rest direction, 13, has none).
+// LDS slot of a moving D3Q27 direction (the rest direction, 13, has none);
+// for D2Q9 (a < 9) the direction itself.
 __host__ __device__ constexpr int nphi_slot(int a) { return a < 13 ? a : a - 1; }
 
 // grad(phi) = (1/cs^2) sum_a w_a c_a phi(x + c_a);
@@ -423,10 +424,10 @@ __device__ __forceinline__ void closure(const Phys<T> &ph, Cell<T> &c)
 // Raw moments of the pulled flow populations (orders 0..2), accumulated over
 // pairs of opposite directions (f_a + f_opp for even moments, f_a - f_opp for
 // odd ones) so that the pressure part w p cancels exactly in the odd moments
-// and the velocity part cancels before it reaches the even ones.  STASH
-// (D3Q27): the pulled values are also kept for a collision that needs them
-// one by one, the moving ones in stash[nphi_slot(a) * sstride], the rest
-// value in *stash_rest.
+// and the velocity part cancels before it reaches the even ones.  STASH: the
+// pulled values are also kept for a collision that needs them one by one,
+// the moving ones in stash[nphi_slot(a) * sstride], the rest value in
+// *stash_rest.
 template <int D, class P, bool STASH, class NB>
 __device__ __forceinline__ void flow_moments(const NB &nb, long long np, const Ptrs &p,
                                              Cell<typename P::T> &c, typename P::T *stash,
@@ -628,8 +629,8 @@ __device__ __forceinline__ void eval_cell16_hoisted(const NB &nb, long long np, 
     velocity<D, float>(c);
 }
 
-// STASH (D3Q27, not where both sets are FP16): the pulled flow values,
-// decoded, are also kept as flow_moments describes.
+// STASH (not where both sets are FP16): the pulled flow values, decoded, are
+// also kept as flow_moments describes.
 template <int D, class P, bool STASH = false, class NB>
 __device__ __forceinline__ void eval_cell(const NB &nb, long long np,
                                           const Phys<typename P::T> &ph, const Ptrs &p,
@@ -920,13 +921,21 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
     // FP16 phase-field storage: fp16 order parameters of the cells that read
     // the phase-field values stored here (see eval_cell16_paired)
     unsigned gref[P::G::shifted ? Q / 2 : 1];
-    // single relaxation time needs the pulled flow values one by one: where
-    // the LDS slots of the stored phase-field values are free until the flow
-    // collision (the flow set collides first), the moment pass leaves them
-    // there instead of the collision pulling them from memory again
-    constexpr bool STASH = KEEP && (COLL & 1) && D == 3 && !P::G::shifted;
-    eval_cell<D, P, STASH>(nb, g.np, ph, p, c, P::G::shifted ? gref : nullptr, keep, kstride,
-                           keep_rest);
+    // single relaxation time needs the pulled flow values one by one: the
+    // moment pass keeps them instead of the collision pulling them from
+    // memory again, in 3-D in the LDS slots of the stored phase-field values
+    // where those are free until the flow collision (the flow set collides
+    // first), in 2-D (eight values) in registers
+    constexpr bool STASH_LDS = KEEP && (COLL & 1) && D == 3 && !P::G::shifted;
+    constexpr bool STASH_REG = !KEEP && (COLL & 1) && D == 2 && !P::G::shifted;
+    constexpr bool STASH = STASH_LDS || STASH_REG;
+    T fkeep[STASH_REG ? Q : 1];
+    T fkeep_rest = 0;
+    T *const stash = STASH_LDS ? keep : fkeep;
+    T *const stash_rest = STASH_LDS ? keep_rest : &fkeep_rest;
+    const int sstride = STASH_LDS ? kstride : 1;
+    eval_cell<D, P, STASH>(nb, g.np, ph, p, c, P::G::shifted ? gref : nullptr, stash, sstride,
+                           stash_rest);
     // Scheduling fences between the phases of the cell update keep the
     // compiler from hoisting every load of the kernel to its start, which
     // would hold them all in registers at once (spills, lower occupancy).
@@ -1032,7 +1041,7 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
                 const int cx = cx_of(a), cy = cy_of(a), cz = cz_of<D>(a);
                 T v;
                 if constexpr (STASH) {
-                    v = a == Q / 2 ? *keep_rest : keep[nphi_slot(a) * kstride];
+                    v = a == Q / 2 ? *stash_rest : stash[nphi_slot(a) * sstride];
                 } else if constexpr (P::F::shifted) {
                     // decode with the writer's reference, from its record
                     const unsigned long long *rec = static_cast<const unsigned long long *>(p.phi);
