@@ -906,6 +906,20 @@ __device__ __forceinline__ typename P::T phi_cell(const Geom &g, const Ptrs &p, 
 // the rest direction's to *keep_rest, for the
 // partial sums of the next order parameter.
 
+// Single relaxation time in the 3-D update without partial sums keeps its
+// pulled flow values in dynamic LDS, 26 per thread (the launch provides these
+// bytes; a block has at most 256 threads); no LDS otherwise.
+template <int D, class P, int COLL>
+constexpr bool srt_lds_stash()
+{
+    return (COLL & 1) && D == 3 && !P::G::shifted;
+}
+template <int D, class P, int COLL>
+constexpr size_t srt_lds_bytes(unsigned threads)
+{
+    return srt_lds_stash<D, P, COLL>() ? size_t(26) * threads * sizeof(typename P::T) : 0;
+}
+
 template <int D, class P, int COLL, class NB, bool KEEP = false>
 __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
                                              const Phys<typename P::T> &ph, const Ptrs &p,
@@ -923,17 +937,28 @@ __device__ __forceinline__ void collide_body(const NB &nb, const Geom &g,
     unsigned gref[P::G::shifted ? Q / 2 : 1];
     // single relaxation time needs the pulled flow values one by one: the
     // moment pass keeps them instead of the collision pulling them from
-    // memory again, in 3-D in the LDS slots of the stored phase-field values
-    // where those are free until the flow collision (the flow set collides
-    // first), in 2-D (eight values) in registers
+    // memory again.  In 3-D with partial sums: in the LDS slots of the stored
+    // phase-field values, free until the flow collision (the flow set collides
+    // first); in 3-D without: in the launch's dynamic LDS; in 2-D (eight
+    // values): in registers
     constexpr bool STASH_LDS = KEEP && (COLL & 1) && D == 3 && !P::G::shifted;
+    constexpr bool STASH_DYN = !KEEP && srt_lds_stash<D, P, COLL>();
     constexpr bool STASH_REG = !KEEP && (COLL & 1) && D == 2 && !P::G::shifted;
-    constexpr bool STASH = STASH_LDS || STASH_REG;
+    constexpr bool STASH = STASH_LDS || STASH_DYN || STASH_REG;
     T fkeep[STASH_REG ? Q : 1];
     T fkeep_rest = 0;
-    T *const stash = STASH_LDS ? keep : fkeep;
+    T *stash = STASH_LDS ? keep : fkeep;
     T *const stash_rest = STASH_LDS ? keep_rest : &fkeep_rest;
-    const int sstride = STASH_LDS ? kstride : 1;
+    int sstride = STASH_LDS ? kstride : 1;
+    if constexpr (STASH_DYN) {
+        // slot s of thread t at [s * threads + t]: each thread its own slots,
+        // consecutive threads in consecutive words
+        extern __shared__ double srt_lds[];
+        const int threads = int(blockDim.x * blockDim.y * blockDim.z);
+        const int tid = int(threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z));
+        stash = reinterpret_cast<T *>(srt_lds) + tid;
+        sstride = threads;
+    }
     eval_cell<D, P, STASH>(nb, g.np, ph, p, c, P::G::shifted ? gref : nullptr, stash, sstride,
                            stash_rest);
     // Scheduling fences between the phases of the cell update keep the

@@ -106,8 +106,8 @@ hipError_t launch_batch_step(int dim, int storage, int collision, bool row,
     c.dim = dim;
     c.storage = storage;
 
-    auto go = [&](auto k, dim3 blk, int nblk) {
-        hipLaunchKernelGGL(k, dim3(nblk), blk, 0, stream, doms, tiles, ntiles, tbase, step_off,
+    auto go = [&](auto k, dim3 blk, int nblk, size_t lds = 0) {
+        hipLaunchKernelGGL(k, dim3(nblk), blk, lds, stream, doms, tiles, ntiles, tbase, step_off,
                            status);
         return hipGetLastError();
     };
@@ -145,8 +145,10 @@ hipError_t launch_batch_step(int dim, int storage, int collision, bool row,
         if (e != hipSuccess) return e;
         return with_coll(collision, [&](auto cc) {
             constexpr int COLL = decltype(cc)::value;
-            hipError_t e2 = row ? go(kb_step<D, P, COLL, false, true>, block, grid[1])
-                                : go(kb_step<D, P, COLL, false, false>, block, grid[1]);
+            // dynamic LDS: single relaxation time's flow values (3-D)
+            const size_t lds = srt_lds_bytes<D, P, COLL>(block.x * block.y * block.z);
+            hipError_t e2 = row ? go(kb_step<D, P, COLL, false, true>, block, grid[1], lds)
+                                : go(kb_step<D, P, COLL, false, false>, block, grid[1], lds);
             const bool nphi = grid[2] || grid[3] || grid[4] || grid[5] || grid[6];
             if constexpr (D == 3) {
                 if (e2 == hipSuccess && nphi) e2 = go_nphi.template operator()<P>(cc);

@@ -51,11 +51,13 @@ hipError_t launch_collide(const Ctx &c)
         const bool row = row_form(c);
         return with_coll(coll_code(c.ph), [&](auto cc) {
             constexpr int COLL = decltype(cc)::value;
+            // dynamic LDS: single relaxation time's flow values (3-D)
+            const size_t lds = srt_lds_bytes<D, P, COLL>(c.block.x * c.block.y * c.block.z);
             if (row)
-                hipLaunchKernelGGL((k_collide<D, P, COLL, true>), grid_for(c), c.block, 0, c.stream,
-                                   c.g, to_phys<T>(c.ph), c.p);
+                hipLaunchKernelGGL((k_collide<D, P, COLL, true>), grid_for(c), c.block, lds,
+                                   c.stream, c.g, to_phys<T>(c.ph), c.p);
             else
-                hipLaunchKernelGGL((k_collide<D, P, COLL, false>), grid_for(c), c.block, 0,
+                hipLaunchKernelGGL((k_collide<D, P, COLL, false>), grid_for(c), c.block, lds,
                                    c.stream, c.g, to_phys<T>(c.ph), c.p);
             return hipGetLastError();
         });
